@@ -1,0 +1,78 @@
+"""Per-unit brute force for tiny grids -- TEST INFRASTRUCTURE.
+
+For every unit of the image, clip the ray's line against that unit's box
+(Liang-Barsky slab clipping) and report the length inside it.  This is the plain
+definition of the intersection length (Sec. 2.2.1 eq. intersection_length,
+Sec. 3.2.1 eq. intersection_length_3D) evaluated unit by unit over all N^d units,
+with no ordering or range logic.  Axes along which the ray does not move use the
+half-open membership of the ambiguity resolution (Sec. 4.1: the unit with the
+bigger 1D index wins): x in [lo, hi), y in (lo, hi], z in (lo, hi].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _axis_bounds(n, d, c, sign):
+    """Physical [lo, hi] of the n units along one axis.  sign=+1: index grows with the
+    coordinate (x); sign=-1: index grows against it (y, z)."""
+    q = np.arange(n, dtype=np.float64)
+    if sign > 0:
+        lo = c + (q - n / 2.0) * d
+        hi = c + (q - n / 2.0 + 1.0) * d
+    else:
+        lo = c + (n / 2.0 - q - 1.0) * d
+        hi = c + (n / 2.0 - q) * d
+    return lo, hi
+
+
+def unit_lengths(g: dict, p, th):
+    """Dense array (image shape) of len(ray, unit) for every unit."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    th = np.asarray(th, dtype=np.float64).ravel()
+    nz = int(g.get("nz", 0))
+    dims = [("nx", "dx", "cx", +1), ("ny", "dy", "cy", -1)]
+    if nz > 0:
+        dims.append(("nz", "dz", "cz", -1))
+    tlo, thi, member = [], [], []
+    for a, (kn, kd, kc, sgn) in enumerate(dims):
+        n = int(g[kn])
+        lo, hi = _axis_bounds(n, float(g.get(kd, 1.0)), float(g.get(kc, 0.0)), sgn)
+        if th[a] != 0.0:
+            t0 = (lo - p[a]) / th[a]
+            t1 = (hi - p[a]) / th[a]
+            tlo.append(np.minimum(t0, t1))
+            thi.append(np.maximum(t0, t1))
+            member.append(np.ones(n, dtype=bool))
+        else:
+            if sgn > 0:
+                m = (lo <= p[a]) & (p[a] < hi)
+            else:
+                m = (lo < p[a]) & (p[a] <= hi)
+            tlo.append(np.full(n, -np.inf))
+            thi.append(np.full(n, np.inf))
+            member.append(m)
+    if nz > 0:
+        # axis order of the array: [k][j][i]
+        L = np.maximum(np.maximum(tlo[2][:, None, None], tlo[1][None, :, None]), tlo[0][None, None, :])
+        U = np.minimum(np.minimum(thi[2][:, None, None], thi[1][None, :, None]), thi[0][None, None, :])
+        M = member[2][:, None, None] & member[1][None, :, None] & member[0][None, None, :]
+    else:
+        L = np.maximum(tlo[1][:, None], tlo[0][None, :])
+        U = np.minimum(thi[1][:, None], thi[0][None, :])
+        M = member[1][:, None] & member[0][None, :]
+    ln = np.where(M, np.maximum(U - L, 0.0), 0.0)
+    return ln
+
+
+def hits(g: dict, p, th, eps=0.0):
+    """(1D indices, lengths) with length > eps, sorted by index."""
+    ln = unit_lengths(g, p, th).ravel()
+    idx = np.nonzero(ln > eps)[0]
+    return idx.astype(np.int64), ln[idx]
+
+
+def matrix(g: dict, lines_p, lines_th):
+    """Dense projection matrix A[ray, unit] (tiny grids only)."""
+    rows = [unit_lengths(g, lines_p[r], lines_th[r]).ravel() for r in range(len(lines_p))]
+    return np.stack(rows, axis=0)
