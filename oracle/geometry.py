@@ -28,8 +28,9 @@ Readings where the paper is silent (each listed in the design notes):
 * detector bins: centre of bin c is u_c = (c - (n-1)/2) du + u0, rows likewise with +z;
 * a flat detector at source-to-detector distance SDD samples the paper's virtual
   detector through the origin at t = u SOD/SDD, h = v SOD/SDD;
-* a direction component with |theta_a| <= 1e-12 is snapped to exactly 0 (so that
-  phi = pi/2 in floating point is the axis-parallel case of the paper).
+* components of magnitude <= 1e-12 of theta, theta_perp, theta_1 and theta_2 are
+  snapped to exactly 0 (so that phi = pi/2 in floating point is the axis-parallel case
+  of the paper, and a ray placed on a grid line or plane by its offsets stays on it).
 """
 from __future__ import annotations
 
@@ -83,11 +84,12 @@ def cone_equispaced(D, phi1p, t, h, H=0.0):
 
 # ------------------------------------------------------------------ parallel params -> lines
 
-def _snap(th):
-    th = np.array(th, dtype=np.float64, copy=True)
-    th[np.abs(th) <= SNAP] = 0.0
-    th /= np.linalg.norm(th, axis=-1, keepdims=True)
-    return th
+def _snap(v, normalise=True):
+    v = np.array(v, dtype=np.float64, copy=True)
+    v[np.abs(v) <= SNAP] = 0.0
+    if normalise:
+        v /= np.linalg.norm(v, axis=-1, keepdims=True)
+    return v
 
 
 def par2d_lines(s, phi):
@@ -96,7 +98,7 @@ def par2d_lines(s, phi):
     phi = np.atleast_1d(np.asarray(phi, dtype=np.float64))
     s, phi = np.broadcast_arrays(s, phi)
     th = np.stack([np.cos(phi), np.sin(phi), np.zeros_like(phi)], axis=-1)
-    perp = np.stack([-np.sin(phi), np.cos(phi), np.zeros_like(phi)], axis=-1)
+    perp = _snap(np.stack([-np.sin(phi), np.cos(phi), np.zeros_like(phi)], axis=-1), False)
     p = s[..., None] * perp
     return p.reshape(-1, 3), _snap(th).reshape(-1, 3)
 
@@ -107,8 +109,8 @@ def par3d_lines(s1, s2, phi1, phi2):
                                                for a in (s1, s2, phi1, phi2)])
     c1, si1, c2, si2 = np.cos(phi1), np.sin(phi1), np.cos(phi2), np.sin(phi2)
     th = np.stack([c2 * c1, c2 * si1, si2], axis=-1)
-    th1 = np.stack([-si1, c1, np.zeros_like(c1)], axis=-1)
-    th2 = np.stack([-si2 * c1, -si2 * si1, c2], axis=-1)
+    th1 = _snap(np.stack([-si1, c1, np.zeros_like(c1)], axis=-1), False)
+    th2 = _snap(np.stack([-si2 * c1, -si2 * si1, c2], axis=-1), False)
     p = s1[..., None] * th1 + s2[..., None] * th2
     return p.reshape(-1, 3), _snap(th).reshape(-1, 3)
 

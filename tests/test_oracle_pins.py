@@ -205,6 +205,35 @@ def test_outer_boundary_rays():
         assert abs(core.forward_lines(g, p, th, img).sum() - img.sum()) < 1e-12
 
 
+def test_axis_aligned_frames_are_exact():
+    # at multiples of pi/2 (and phi2 = +-pi/4) the frame vectors of eqs. theta_1, theta_2
+    # take exact values; a grid-aligned ray must stay on its grid line/plane
+    r = math.sqrt(0.5)
+    exact_cs = {0.0: (1.0, 0.0), PI / 2: (0.0, 1.0), PI: (-1.0, 0.0), 3 * PI / 2: (0.0, -1.0),
+                PI / 4: (r, r), -PI / 4: (r, -r)}
+    for p1 in (0.0, PI / 2, PI, 3 * PI / 2):
+        for p2 in (0.0, PI / 4, -PI / 4):
+            for s1, s2 in ((-4.5, 3.5), (2.0, -1.0), (0.5, 0.0)):
+                c1, n1 = exact_cs[p1]
+                c2, n2 = exact_cs[p2]
+                th = np.array([c2 * c1, c2 * n1, n2])
+                t1 = np.array([-n1, c1, 0.0])
+                t2 = np.array([-n2 * c1, -n2 * n1, c2])
+                p, t = G.par3d_lines(s1, s2, p1, p2)
+                ref = s1 * t1 + s2 * t2
+                np.testing.assert_allclose(p[0], ref, rtol=0, atol=1e-14)
+                for a in range(3):   # coordinates fixed by exact frame entries are exact
+                    if t1[a] in (-1.0, 0.0, 1.0) and t2[a] in (-1.0, 0.0, 1.0):
+                        assert p[0][a] == ref[a]
+                np.testing.assert_allclose(t[0], th, rtol=0, atol=1e-15)
+                assert np.all((t[0] == 0) == (th == 0))
+    for phi in (0.0, PI / 2, PI, 3 * PI / 2):
+        c, n = exact_cs[phi]
+        p, t = G.par2d_lines(2.5, phi)
+        np.testing.assert_array_equal(p[0], 2.5 * np.array([-n, c, 0.0]))
+        assert np.all((t[0] == 0) == (np.array([c, n, 0.0]) == 0))
+
+
 # ------------------------------------------------------------------ brute force on random rays
 
 def _random_grid(rng, d3):
