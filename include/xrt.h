@@ -1,0 +1,150 @@
+/*
+ * xrt.h -- C ABI of libxrt.so, the MI355X (gfx950) implementation of the discrete
+ * X-ray transform of a pixel/voxel image and of its adjoint.
+ *
+ * Reference: C. Chen, R. Wang, C. Bajaj, O. Oktem, "A Fast and Adaptive Algorithm to
+ * Compute the X-ray Transform" (arXiv 2006.00686).
+ *
+ * What is computed (Introduction, eq. Xray_transform_image; Secs. 2.2.1 and 3.2.1):
+ *   image f = sum_I f_I b_I with b_I the indicator of unit I (pixel or voxel);
+ *   for every ray r,  g_r = sum_I f_I * len(r, I),  len = length of the ray inside
+ *   unit I; the adjoint is f_I = sum_r g_r * len(r, I) (the transpose of the
+ *   projection matrix, Introduction).  For each ray only the units that the paper's
+ *   sufficient-and-necessary condition (eqs. conditions_2D_1, conditions_3D_1) admits
+ *   are visited, and len = C_up - C_low (eqs. range_length, range_length_3D).
+ *
+ * Image layout: unit (k, j, i) has centre (cx + (i - (nx-1)/2) dx, cy + ((ny-1)/2 - j) dy,
+ *   cz + ((nz-1)/2 - k) dz) (Secs. 2.1 and 3.1 with scale and offset, Sec. 4.2); the
+ *   1D index is I = (k*ny + j)*nx + i (the paper's kNyNx + jNy + i for non-square
+ *   grids).  Buffers are float32, contiguous, [batch][nz][ny][nx] ([batch][ny][nx] in 2D).
+ * Sinogram layout: float32 [batch][view][row][col] (2D kinds: [batch][view][col];
+ *   ray lists: [batch][ray]).
+ * Grid-aligned rays (Sec. 4.1): a ray lying on a grid line/plane is given to the unit
+ *   with the bigger 1D index (half-open units: x in [lo,hi), y in (lo,hi], z in (lo,hi]),
+ *   also at the outer border of the image.
+ *
+ * Ownership: the caller allocates and owns every buffer passed in (device pointers
+ *   marked d_, host pointers otherwise).  A plan owns its device tables; destroy frees
+ *   them.  Host arrays referenced by xrt_scan are copied during xrt_plan_create.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *   asynchronously; no call below synchronises the host except plan create/destroy.
+ * Errors: every call returns an xrt_status.  Arguments are validated before any work
+ *   is enqueued, so a failed call writes nothing.  XRT_E_HIP carries the HIP runtime
+ *   message in xrt_last_error() (per thread).
+ */
+#ifndef XRT_H
+#define XRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum xrt_status {
+    XRT_OK = 0,
+    XRT_E_ARG = -1,          /* null pointer, unknown enum value, batch < 1, bad ray range */
+    XRT_E_GEOM = -2,         /* invalid geometry: non-positive sizes or spacings, SOD/SDD <= 0,
+                                source inside the image box, non-finite parameters */
+    XRT_E_SIZE = -3,         /* more than 2^31-1 units, or sizes beyond the library's limits */
+    XRT_E_HIP = -4,          /* a HIP runtime call failed (see xrt_last_error) */
+    XRT_E_NOMEM = -5,        /* device or host allocation failed */
+    XRT_E_UNSUPPORTED = -6   /* valid request that this build does not implement */
+} xrt_status;
+
+/* Scan kinds.  Bin centres are u_c = (c - (n_cols-1)/2)*du + u0 and
+ * v_r = (r - (n_rows-1)/2)*dv + v0 (v grows with +z). */
+typedef enum xrt_kind {
+    XRT_PAR2D = 1,      /* 2D parallel beam (Sec. 2.2.1): view angle phi, bin = s          */
+    XRT_FAN2D_FLAT = 2, /* equispaced fan (Sec. 2.2.2, eq. 2Dparalleltofan_2): view angle
+                           alpha (source at sod*(-sin a, cos a)), flat detector at sdd     */
+    XRT_FAN2D_ARC = 3,  /* equiangular fan (eq. 2Dparalleltofan): bin = gamma [rad]      */
+    XRT_PAR3D = 4,      /* 3D parallel beam (Sec. 3.2.1): view (phi1, phi2), bins (s1, s2) */
+    XRT_CONE_FLAT = 5,  /* equispaced circular/helical cone (Secs. 3.2.2-3.2.3): view
+                           angle phi1' (source at -sod*(cos p, sin p, 0) + (0,0,H)),
+                           flat detector at sdd with u along (-sin p, cos p, 0), v along z */
+    XRT_CONE_ARC = 6,   /* equiangular cone: bins (alpha, beta) [rad]                     */
+    XRT_RAYLIST2D = 7,  /* explicit rays (s, phi) (Sec. 4.2: any ray given by its
+                           parallel-beam parameters)                                       */
+    XRT_RAYLIST3D = 8   /* explicit rays (s1, s2, phi1, phi2)                              */
+} xrt_kind;
+
+typedef struct xrt_grid {
+    int32_t nx, ny, nz;     /* units per axis; nz = 0 selects a 2D image               */
+    double dx, dy, dz;      /* unit side lengths (> 0); dz ignored in 2D                 */
+    double cx, cy, cz;      /* centre of the image box                                   */
+} xrt_grid;
+
+typedef struct xrt_scan {
+    int32_t kind;                  /* xrt_kind                                         */
+    int32_t n_views, n_rows, n_cols; /* n_rows = 1 for 2D kinds; ignored for ray lists  */
+    double du, dv, u0, v0;         /* bin spacing and offset (radians for ARC kinds)    */
+    double sod, sdd;               /* source-to-centre, source-to-detector (divergent)  */
+    const double* view_angle;      /* host [n_views]: phi, alpha, phi1 or phi1'         */
+    const double* view_z;          /* host [n_views] or NULL: source height H (cone);
+                                      non-NULL makes the cone helical                  */
+    const double* view_phi2;       /* host [n_views]: elevation phi2 (PAR3D only)       */
+    const double* ray_params;      /* host [n_rays][2 or 4] (RAYLIST kinds only)        */
+    int64_t n_rays;                /* RAYLIST kinds only                                */
+} xrt_scan;
+
+typedef struct xrt_plan xrt_plan;
+
+/* Adjoint algorithms (Introduction: the adjoint is the transpose of the projection
+ * matrix).  SCATTER walks the rays with the forward traversal and adds g_r * len into
+ * the image with float atomics (order-dependent rounding); GATHER visits every unit
+ * and sums over the rays that hit it, in a fixed order (deterministic); AUTO takes
+ * the faster one for the plan's geometry. */
+typedef enum xrt_adjoint_mode {
+    XRT_ADJ_AUTO = 0,
+    XRT_ADJ_SCATTER = 1,
+    XRT_ADJ_GATHER = 2
+} xrt_adjoint_mode;
+
+/* Build a plan: validates grid and scan, expands the geometry in FP64 on the host
+ * (Secs. 2.2.2, 3.2.2, 3.2.3 transforms, applied as the equivalent source-to-detector
+ * construction), snaps direction components of magnitude <= 1e-12 to exactly 0, and
+ * uploads the per-view tables to `device`.  Synchronous.  *out is NULL on failure. */
+xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int device,
+                           xrt_plan** out);
+
+/* Free the plan's device tables.  Synchronises the plan's device.  NULL is accepted. */
+xrt_status xrt_plan_destroy(xrt_plan* plan);
+
+/* Number of rays (= sinogram elements per batch member) and of units (image elements
+ * per batch member). */
+xrt_status xrt_plan_sizes(const xrt_plan* plan, int64_t* n_rays, int64_t* n_units);
+
+/* Forward transform: d_sino[b][r] = sum_I d_img[b][I] * len(r, I) for b < batch.
+ * Overwrites d_sino.  d_img and d_sino must not overlap. */
+xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch,
+                       void* stream);
+
+/* Adjoint: d_img[b][I] = sum_r d_sino[b][r] * len(r, I).  Overwrites d_img (the
+ * library clears it with its own kernel first).  mode: xrt_adjoint_mode. */
+xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch,
+                       int32_t mode, void* stream);
+
+/* Number of hit units of rays [first, first+n): d_counts[r] = #{I : len(first+r, I) > eps}
+ * (eps >= 0; eps = 0 is the paper's strict condition C_low < C_up). */
+xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double eps,
+                              int32_t* d_counts, void* stream);
+
+/* Hit lists of rays [first, first+n) (Algorithms 1 and 2: the 1D indices and
+ * intersection lengths of each ray).  Row r occupies d_idx/d_len[d_offsets[r] ..
+ * d_offsets[r] + count_r), count_r as reported by xrt_ray_hit_counts with the same
+ * eps; entries are in order of increasing position along the ray.  d_offsets is
+ * int64 [n]. */
+xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps,
+                        const int64_t* d_offsets, int32_t* d_idx, float* d_len, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* xrt_status_str(int32_t status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* xrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XRT_H */

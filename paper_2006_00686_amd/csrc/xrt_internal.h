@@ -1,0 +1,83 @@
+// Internal types shared by the host side (plan construction) and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/xrt.h"
+
+namespace xrt {
+
+// How a ray (point p, direction d, both FP64, physical units) is built from its
+// (view, row, col) in the kernels.  Every geometry of the paper reduces to one of these
+// (Sec. 4.2: the transform depends only on each ray's geometric parameters).
+enum RayMode : int32_t {
+    MODE_PARALLEL = 0,    // p = A + u B + v C,  d = E            (PAR2D, PAR3D)
+    MODE_DIVERGENT = 1,   // p = A (source),     d = E + u B + v C (flat fan / cone)
+    MODE_ARC = 2,         // p = A, d = cb (ca E + sa B) + sb C    (equiangular fan / cone)
+    MODE_LIST = 3         // p, d read per ray from a table        (ray lists)
+};
+
+struct ViewGeom {         // FP64 per-view vectors, see RayMode
+    double A[3], B[3], C[3], E[3];
+};
+
+// Everything a projection kernel needs, passed by value as a kernel argument.
+struct DevPlan {
+    int32_t dim;          // 2 or 3
+    int32_t mode;         // RayMode
+    int32_t nx, ny, nz;   // nz = 1 in 2D
+    int32_t n_views, n_rows, n_cols;
+    int64_t n_rays;
+    int64_t n_units;
+    // index-space transform: q = (p_x*ax + bx, -p_y*ay + by, -p_z*az + bz),
+    // direction w = (d_x*ax, -d_y*ay, -d_z*az); unit (k,j,i) = [i,i+1)x[j,j+1)x[k,k+1)
+    double ax, bx, ay, by, az, bz;
+    double du, ubase, dv, vbase;      // u = c*du + ubase, v = r*dv + vbase
+    const ViewGeom* views;            // [n_views]
+    const double* col_cs;             // MODE_ARC: [n_cols][2] (cos, sin) of the column angle
+    const double* row_cs;             // MODE_ARC: [n_rows][2]
+    const double* rays;               // MODE_LIST: [n_rays][6] (p, d)
+};
+
+}  // namespace xrt
+
+struct xrt_plan {
+    int device;
+    xrt::DevPlan dp;
+    void* d_views;
+    void* d_col;
+    void* d_row;
+    void* d_rays;
+    int32_t kind;
+};
+
+namespace xrt {
+// Host-side result of validating and expanding a grid + scan (device pointers unset).
+struct HostTables {
+    DevPlan dp;
+    int32_t kind;
+    std::vector<ViewGeom> views;
+    std::vector<double> col, row, rays;
+};
+
+// Validate and expand in FP64 on the host (no HIP calls).
+xrt_status build_tables(const xrt_grid* grid, const xrt_scan* scan, HostTables& out);
+
+// Set by failing entry points; read by xrt_last_error().
+void set_error(const char* fmt, ...);
+xrt_status hip_fail(hipError_t e, const char* what);
+
+// Launchers (xrt_project.hip).
+xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch,
+                          hipStream_t s);
+xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
+                                  hipStream_t s);
+xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps,
+                             int32_t* counts, hipStream_t s);
+xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps,
+                       const int64_t* offsets, int32_t* idx, float* len, hipStream_t s);
+xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s);
+}  // namespace xrt

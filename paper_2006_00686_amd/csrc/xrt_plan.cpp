@@ -1,0 +1,484 @@
+// Host side of libxrt: argument validation, FP64 geometry expansion into per-view
+// tables, plan lifetime and the extern "C" entry points declared in include/xrt.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "xrt_internal.h"
+
+namespace xrt {
+namespace {
+
+thread_local char g_err[512] = "";
+
+constexpr double kSnap = 1e-12;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Unit vector with components of magnitude <= kSnap set to exactly 0, so that a view
+// at phi = pi/2 in floating point is the axis-parallel case of the paper (Case 2 of
+// Sec. 2.2.1; Cases 2-4 of Sec. 3.2.1) and grid-aligned rays take the Sec. 4.1 rule.
+void snap3(double v[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (std::fabs(v[a]) <= kSnap) v[a] = 0.0;
+}
+
+void set3(double* dst, double x, double y, double z)
+{
+    dst[0] = x;
+    dst[1] = y;
+    dst[2] = z;
+}
+
+// 3D parallel-beam frame (Sec. 3.2.1, eqs. 3Dparallel_direction, theta_1, theta_2).
+void frame3d(double phi1, double phi2, double th[3], double th1[3], double th2[3])
+{
+    const double c1 = std::cos(phi1), s1 = std::sin(phi1), c2 = std::cos(phi2), s2 = std::sin(phi2);
+    set3(th, c2 * c1, c2 * s1, s2);
+    set3(th1, -s1, c1, 0.0);
+    set3(th2, -s2 * c1, -s2 * s1, c2);
+    snap3(th);
+    snap3(th1);
+    snap3(th2);
+}
+
+bool is2d(int kind)
+{
+    return kind == XRT_PAR2D || kind == XRT_FAN2D_FLAT || kind == XRT_FAN2D_ARC || kind == XRT_RAYLIST2D;
+}
+
+// Is the point strictly outside the closed image box?
+bool outside_box(const xrt_grid& g, const double S[3])
+{
+    const double hx = 0.5 * g.nx * g.dx, hy = 0.5 * g.ny * g.dy;
+    if (std::fabs(S[0] - g.cx) > hx || std::fabs(S[1] - g.cy) > hy) return true;
+    if (g.nz > 0) {
+        const double hz = 0.5 * g.nz * g.dz;
+        if (std::fabs(S[2] - g.cz) > hz) return true;
+    }
+    return false;
+}
+
+xrt_status validate(const xrt_grid* g, const xrt_scan* s)
+{
+    if (!g || !s) { set_error("null grid or scan"); return XRT_E_ARG; }
+    if (s->kind < XRT_PAR2D || s->kind > XRT_RAYLIST3D) {
+        set_error("unknown scan kind %d", s->kind);
+        return XRT_E_ARG;
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 0) { set_error("grid sizes must be positive"); return XRT_E_GEOM; }
+    if (!(g->dx > 0) || !(g->dy > 0) || !finite(g->dx) || !finite(g->dy) || !finite(g->cx) || !finite(g->cy)) {
+        set_error("grid spacing must be positive and finite");
+        return XRT_E_GEOM;
+    }
+    if (g->nz > 0 && (!(g->dz > 0) || !finite(g->dz) || !finite(g->cz))) {
+        set_error("grid dz must be positive and finite");
+        return XRT_E_GEOM;
+    }
+    const int64_t nu = (int64_t)g->nx * g->ny * (g->nz > 0 ? g->nz : 1);
+    if (nu > INT32_MAX) { set_error("more than 2^31-1 units"); return XRT_E_SIZE; }
+    if (is2d(s->kind) != (g->nz == 0)) {
+        set_error("scan kind %d does not match a %dD grid", s->kind, g->nz == 0 ? 2 : 3);
+        return XRT_E_GEOM;
+    }
+    if (s->kind == XRT_RAYLIST2D || s->kind == XRT_RAYLIST3D) {
+        if (!s->ray_params) { set_error("ray_params is NULL"); return XRT_E_ARG; }
+        if (s->n_rays < 1) { set_error("n_rays must be >= 1"); return XRT_E_GEOM; }
+        if (s->n_rays > INT32_MAX) { set_error("more than 2^31-1 rays"); return XRT_E_SIZE; }
+        const int w = s->kind == XRT_RAYLIST2D ? 2 : 4;
+        for (int64_t i = 0; i < s->n_rays * w; ++i)
+            if (!finite(s->ray_params[i])) { set_error("non-finite ray parameter"); return XRT_E_GEOM; }
+        return XRT_OK;
+    }
+    if (s->n_views < 1 || s->n_cols < 1 || s->n_rows < 1) {
+        set_error("n_views, n_rows, n_cols must be >= 1");
+        return XRT_E_GEOM;
+    }
+    if (is2d(s->kind) && s->n_rows != 1) { set_error("2D scans have n_rows = 1"); return XRT_E_GEOM; }
+    if ((int64_t)s->n_views * s->n_rows * s->n_cols > INT32_MAX) {
+        set_error("more than 2^31-1 rays");
+        return XRT_E_SIZE;
+    }
+    if (!(s->du > 0) || !finite(s->du) || !finite(s->u0)) { set_error("du must be positive"); return XRT_E_GEOM; }
+    if (!is2d(s->kind) && (!(s->dv > 0) || !finite(s->dv) || !finite(s->v0))) {
+        set_error("dv must be positive");
+        return XRT_E_GEOM;
+    }
+    if (!s->view_angle) { set_error("view_angle is NULL"); return XRT_E_ARG; }
+    for (int i = 0; i < s->n_views; ++i) {
+        if (!finite(s->view_angle[i])) { set_error("non-finite view angle"); return XRT_E_GEOM; }
+        if (s->view_z && !finite(s->view_z[i])) { set_error("non-finite view_z"); return XRT_E_GEOM; }
+    }
+    if (s->kind == XRT_PAR3D) {
+        if (!s->view_phi2) { set_error("view_phi2 is NULL"); return XRT_E_ARG; }
+        for (int i = 0; i < s->n_views; ++i)
+            if (!finite(s->view_phi2[i])) { set_error("non-finite view_phi2"); return XRT_E_GEOM; }
+    }
+    const bool divergent = s->kind == XRT_FAN2D_FLAT || s->kind == XRT_FAN2D_ARC ||
+                           s->kind == XRT_CONE_FLAT || s->kind == XRT_CONE_ARC;
+    if (divergent) {
+        if (!(s->sod > 0) || !finite(s->sod)) { set_error("sod must be positive"); return XRT_E_GEOM; }
+        const bool flat = s->kind == XRT_FAN2D_FLAT || s->kind == XRT_CONE_FLAT;
+        if (flat && (!(s->sdd > 0) || !finite(s->sdd))) { set_error("sdd must be positive"); return XRT_E_GEOM; }
+        if (s->kind == XRT_FAN2D_ARC || s->kind == XRT_CONE_ARC) {
+            // equiangular bins must stay inside (-pi/2, pi/2)
+            const double ue = 0.5 * (s->n_cols - 1) * s->du + std::fabs(s->u0);
+            const double ve = 0.5 * (s->n_rows - 1) * s->dv + std::fabs(s->v0);
+            if (ue >= M_PI / 2 || (s->kind == XRT_CONE_ARC && ve >= M_PI / 2)) {
+                set_error("equiangular bins must lie in (-pi/2, pi/2)");
+                return XRT_E_GEOM;
+            }
+        }
+    }
+    return XRT_OK;
+}
+
+// FP64 expansion of the scan into per-view vectors (see RayMode).  The rays are the
+// paper's: eq. 2Dparalleltofan / 2Dparalleltofan_2 for fans, eqs. equiangular_cone_beam,
+// equispaced_cone_beam and the helical variants for cones, written as the line from
+// the source through the detector cell (the same line, cheaper per ray).
+xrt_status expand(const xrt_grid& g, const xrt_scan& s, DevPlan& D, std::vector<ViewGeom>& views,
+                  std::vector<double>& col, std::vector<double>& row, std::vector<double>& rays)
+{
+    const int kind = s.kind;
+    if (kind == XRT_RAYLIST2D || kind == XRT_RAYLIST3D) {
+        D.mode = MODE_LIST;
+        D.n_views = 1;
+        D.n_rows = 1;
+        D.n_cols = (int32_t)s.n_rays;
+        D.n_rays = s.n_rays;
+        rays.resize((size_t)s.n_rays * 6);
+        for (int64_t r = 0; r < s.n_rays; ++r) {
+            double* t = &rays[(size_t)r * 6];
+            if (kind == XRT_RAYLIST2D) {
+                const double sv = s.ray_params[2 * r], phi = s.ray_params[2 * r + 1];
+                double th[3] = {std::cos(phi), std::sin(phi), 0.0};
+                double pe[3] = {-std::sin(phi), std::cos(phi), 0.0};
+                snap3(th);
+                snap3(pe);
+                set3(t, sv * pe[0], sv * pe[1], 0.0);
+                set3(t + 3, th[0], th[1], 0.0);
+            } else {
+                const double* q = s.ray_params + 4 * r;
+                double th[3], t1[3], t2[3];
+                frame3d(q[2], q[3], th, t1, t2);
+                for (int a = 0; a < 3; ++a) {
+                    t[a] = q[0] * t1[a] + q[1] * t2[a];
+                    t[3 + a] = th[a];
+                }
+            }
+        }
+        return XRT_OK;
+    }
+    D.n_views = s.n_views;
+    D.n_rows = s.n_rows;
+    D.n_cols = s.n_cols;
+    D.n_rays = (int64_t)s.n_views * s.n_rows * s.n_cols;
+    D.du = s.du;
+    D.ubase = s.u0 - 0.5 * (s.n_cols - 1) * s.du;
+    D.dv = is2d(kind) ? 0.0 : s.dv;
+    D.vbase = is2d(kind) ? 0.0 : s.v0 - 0.5 * (s.n_rows - 1) * s.dv;
+    views.assign((size_t)s.n_views, ViewGeom{});
+    for (int v = 0; v < s.n_views; ++v) {
+        ViewGeom& V = views[(size_t)v];
+        const double ang = s.view_angle[v];
+        const double H = s.view_z ? s.view_z[v] : 0.0;
+        switch (kind) {
+            case XRT_PAR2D: {   // ray t theta + s theta_perp (Sec. 2.2.1)
+                double th[3] = {std::cos(ang), std::sin(ang), 0.0};
+                double pe[3] = {-std::sin(ang), std::cos(ang), 0.0};
+                snap3(th);
+                snap3(pe);
+                set3(V.A, 0, 0, 0);
+                std::memcpy(V.B, pe, sizeof pe);
+                set3(V.C, 0, 0, 0);
+                std::memcpy(V.E, th, sizeof th);
+                D.mode = MODE_PARALLEL;
+                break;
+            }
+            case XRT_PAR3D: {   // ray t theta + s1 theta_1 + s2 theta_2 (Sec. 3.2.1)
+                double th[3], t1[3], t2[3];
+                frame3d(ang, s.view_phi2[v], th, t1, t2);
+                set3(V.A, 0, 0, 0);
+                std::memcpy(V.B, t1, sizeof t1);
+                std::memcpy(V.C, t2, sizeof t2);
+                std::memcpy(V.E, th, sizeof th);
+                D.mode = MODE_PARALLEL;
+                break;
+            }
+            case XRT_FAN2D_FLAT:
+            case XRT_FAN2D_ARC: {
+                // source at D(-sin a, cos a); central ray e = (sin a, -cos a) through the
+                // origin; positive bins rotate the ray counter-clockwise, b = (cos a, sin a)
+                double e[3] = {std::sin(ang), -std::cos(ang), 0.0};
+                double b[3] = {std::cos(ang), std::sin(ang), 0.0};
+                snap3(e);
+                snap3(b);
+                set3(V.A, -s.sod * e[0], -s.sod * e[1], 0.0);
+                if (kind == XRT_FAN2D_FLAT) {
+                    set3(V.E, s.sdd * e[0], s.sdd * e[1], 0.0);
+                    D.mode = MODE_DIVERGENT;
+                } else {
+                    std::memcpy(V.E, e, sizeof e);
+                    D.mode = MODE_ARC;
+                }
+                std::memcpy(V.B, b, sizeof b);
+                set3(V.C, 0, 0, 0);
+                if (!outside_box(g, V.A)) {
+                    set_error("view %d: source inside the image box", v);
+                    return XRT_E_GEOM;
+                }
+                break;
+            }
+            default: {   // XRT_CONE_FLAT, XRT_CONE_ARC
+                // source at -D (cos p, sin p, 0) + (0, 0, H); u along (-sin p, cos p, 0), v along z
+                double e[3] = {std::cos(ang), std::sin(ang), 0.0};
+                double b[3] = {-std::sin(ang), std::cos(ang), 0.0};
+                snap3(e);
+                snap3(b);
+                set3(V.A, -s.sod * e[0], -s.sod * e[1], H);
+                if (kind == XRT_CONE_FLAT) {
+                    set3(V.E, s.sdd * e[0], s.sdd * e[1], 0.0);
+                    D.mode = MODE_DIVERGENT;
+                } else {
+                    std::memcpy(V.E, e, sizeof e);
+                    D.mode = MODE_ARC;
+                }
+                std::memcpy(V.B, b, sizeof b);
+                set3(V.C, 0, 0, 1.0);
+                if (!outside_box(g, V.A)) {
+                    set_error("view %d: source inside the image box", v);
+                    return XRT_E_GEOM;
+                }
+                break;
+            }
+        }
+    }
+    if (D.mode == MODE_ARC) {
+        col.resize((size_t)s.n_cols * 2);
+        row.resize((size_t)s.n_rows * 2);
+        for (int c = 0; c < s.n_cols; ++c) {
+            const double a = D.ubase + c * s.du;
+            col[2 * c] = std::cos(a);
+            col[2 * c + 1] = std::sin(a);
+        }
+        for (int r = 0; r < s.n_rows; ++r) {
+            const double b = is2d(kind) ? 0.0 : D.vbase + r * s.dv;
+            row[2 * r] = std::cos(b);
+            row[2 * r + 1] = std::sin(b);
+        }
+    }
+    return XRT_OK;
+}
+
+template <class T>
+xrt_status upload(const std::vector<T>& h, void** d)
+{
+    *d = nullptr;
+    if (h.empty()) return XRT_OK;
+    hipError_t e = hipMalloc(d, h.size() * sizeof(T));
+    if (e != hipSuccess) {
+        *d = nullptr;
+        (void)hipGetLastError();
+        set_error("hipMalloc of %zu bytes failed: %s", h.size() * sizeof(T), hipGetErrorString(e));
+        return XRT_E_NOMEM;
+    }
+    return hip_fail(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+void free_plan(xrt_plan* p)
+{
+    if (!p) return;
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays})
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+}  // namespace
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+xrt_status hip_fail(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return XRT_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return XRT_E_HIP;
+}
+
+xrt_status build_tables(const xrt_grid* grid, const xrt_scan* scan, HostTables& T)
+{
+    xrt_status st = validate(grid, scan);
+    if (st != XRT_OK) return st;
+    const xrt_grid& g = *grid;
+    T = HostTables{};
+    T.kind = scan->kind;
+    DevPlan& D = T.dp;
+    D.dim = g.nz > 0 ? 3 : 2;
+    D.nx = g.nx;
+    D.ny = g.ny;
+    D.nz = g.nz > 0 ? g.nz : 1;
+    D.n_units = (int64_t)D.nx * D.ny * D.nz;
+    D.ax = 1.0 / g.dx;
+    D.bx = 0.5 * g.nx - g.cx * D.ax;
+    D.ay = 1.0 / g.dy;
+    D.by = 0.5 * g.ny + g.cy * D.ay;
+    if (g.nz > 0) {
+        D.az = 1.0 / g.dz;
+        D.bz = 0.5 * g.nz + g.cz * D.az;
+    } else {
+        D.az = 0.0;
+        D.bz = 0.5;
+    }
+    return expand(g, *scan, D, T.views, T.col, T.row, T.rays);
+}
+
+}  // namespace xrt
+
+using namespace xrt;
+
+extern "C" {
+
+xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int device, xrt_plan** out)
+{
+    if (!out) { set_error("out is NULL"); return XRT_E_ARG; }
+    *out = nullptr;
+    HostTables T;
+    xrt_status st = build_tables(grid, scan, T);
+    if (st != XRT_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        set_error("device %d not available (%d devices)", device, ndev);
+        return XRT_E_ARG;
+    }
+    xrt_plan* p = new (std::nothrow) xrt_plan{};
+    if (!p) { set_error("host allocation failed"); return XRT_E_NOMEM; }
+    p->device = device;
+    p->kind = T.kind;
+    p->dp = T.dp;
+    DeviceGuard guard(device);
+    if (!guard.ok) { delete p; set_error("hipSetDevice(%d) failed", device); return XRT_E_HIP; }
+    if ((st = upload(T.views, &p->d_views)) != XRT_OK || (st = upload(T.col, &p->d_col)) != XRT_OK ||
+        (st = upload(T.row, &p->d_row)) != XRT_OK || (st = upload(T.rays, &p->d_rays)) != XRT_OK) {
+        free_plan(p);
+        return st;
+    }
+    DevPlan& D = p->dp;
+    D.views = (const ViewGeom*)p->d_views;
+    D.col_cs = (const double*)p->d_col;
+    D.row_cs = (const double*)p->d_row;
+    D.rays = (const double*)p->d_rays;
+    *out = p;
+    return XRT_OK;
+}
+
+xrt_status xrt_plan_destroy(xrt_plan* plan)
+{
+    if (!plan) return XRT_OK;
+    DeviceGuard guard(plan->device);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return XRT_OK;
+}
+
+xrt_status xrt_plan_sizes(const xrt_plan* plan, int64_t* n_rays, int64_t* n_units)
+{
+    if (!plan) { set_error("plan is NULL"); return XRT_E_ARG; }
+    if (n_rays) *n_rays = plan->dp.n_rays;
+    if (n_units) *n_units = plan->dp.n_units;
+    return XRT_OK;
+}
+
+xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_forward(plan, d_img, d_sino, batch, (hipStream_t)stream);
+}
+
+xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
+                       void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    if (mode != XRT_ADJ_AUTO && mode != XRT_ADJ_SCATTER && mode != XRT_ADJ_GATHER) {
+        set_error("unknown adjoint mode %d", mode);
+        return XRT_E_ARG;
+    }
+    if (mode == XRT_ADJ_GATHER) {
+        set_error("gather adjoint not available for this plan");
+        return XRT_E_UNSUPPORTED;
+    }
+    DeviceGuard guard(plan->device);
+    return launch_adjoint_scatter(plan, d_sino, d_img, batch, (hipStream_t)stream);
+}
+
+xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double eps, int32_t* d_counts,
+                              void* stream)
+{
+    if (!plan || !d_counts) { set_error("null argument"); return XRT_E_ARG; }
+    if (first < 0 || n < 0 || first + n > plan->dp.n_rays || !(eps >= 0)) {
+        set_error("bad ray range or eps");
+        return XRT_E_ARG;
+    }
+    DeviceGuard guard(plan->device);
+    return launch_hit_counts(plan, first, n, eps, d_counts, (hipStream_t)stream);
+}
+
+xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps, const int64_t* d_offsets,
+                        int32_t* d_idx, float* d_len, void* stream)
+{
+    if (!plan || !d_offsets || !d_idx || !d_len) { set_error("null argument"); return XRT_E_ARG; }
+    if (first < 0 || n < 0 || first + n > plan->dp.n_rays || !(eps >= 0)) {
+        set_error("bad ray range or eps");
+        return XRT_E_ARG;
+    }
+    DeviceGuard guard(plan->device);
+    return launch_hits(plan, first, n, eps, d_offsets, d_idx, d_len, (hipStream_t)stream);
+}
+
+const char* xrt_status_str(int32_t status)
+{
+    switch (status) {
+        case XRT_OK: return "XRT_OK";
+        case XRT_E_ARG: return "XRT_E_ARG (invalid argument)";
+        case XRT_E_GEOM: return "XRT_E_GEOM (invalid geometry)";
+        case XRT_E_SIZE: return "XRT_E_SIZE (size limit exceeded)";
+        case XRT_E_HIP: return "XRT_E_HIP (HIP runtime error)";
+        case XRT_E_NOMEM: return "XRT_E_NOMEM (allocation failed)";
+        case XRT_E_UNSUPPORTED: return "XRT_E_UNSUPPORTED";
+        default: return "unknown xrt_status";
+    }
+}
+
+const char* xrt_last_error(void) { return g_err; }
+
+}  // extern "C"

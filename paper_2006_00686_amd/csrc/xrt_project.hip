@@ -1,0 +1,242 @@
+// Ray-driven kernels of the discrete X-ray transform for gfx950: forward projection,
+// scatter adjoint and per-ray hit lists.  The per-ray work (ray construction, clip, slab
+// walk with the paper's range condition and length formula) is in xrt_walk.h.
+//
+// One lane per ray; a wavefront holds 64 consecutive detector columns of one (view, row),
+// so neighbouring lanes walk neighbouring, nearly parallel rays through the same part of
+// the image.  Image and sinogram data are float32; line integrals accumulate in FP64.
+#include "xrt_walk.h"
+
+namespace xrt {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Visitors receive the candidates of one slab.  The first candidate (the unit the ray is
+// in at slab entry) always has a valid index; the others are only valid when their
+// length is positive.
+//
+// Forward: the gathers are issued unconditionally, a candidate that is not hit reads the
+// entry unit instead (same cache line, always in range) and is weighted by 0, so the
+// three loads of a slab are in flight together instead of each behind its own branch.
+struct FwdVisit {
+    const float* __restrict__ img;
+    double acc;
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        const bool h2 = l2 > 0.0;
+        const float f1 = img[I1];
+        const float f2 = img[h2 ? I2 : I1];
+        acc = fma((double)f1, fmax(l1, 0.0), acc);
+        acc = fma((double)f2, h2 ? l2 : 0.0, acc);
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        const bool h2 = l2 > 0.0, h3 = l3 > 0.0;
+        const float f1 = img[I1];
+        const float f2 = img[h2 ? I2 : I1];
+        const float f3 = img[h3 ? I3 : I1];
+        acc = fma((double)f1, fmax(l1, 0.0), acc);
+        acc = fma((double)f2, h2 ? l2 : 0.0, acc);
+        acc = fma((double)f3, h3 ? l3 : 0.0, acc);
+    }
+};
+
+struct ScatterVisit {
+    float* img;
+    double gw;
+    __device__ __forceinline__ void one(int32_t I, double l)
+    {
+        if (l > 0.0) unsafeAtomicAdd(img + I, (float)(gw * l));
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        one(I1, l1);
+        one(I2, l2);
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        one(I1, l1);
+        one(I2, l2);
+        one(I3, l3);
+    }
+};
+
+struct CountVisit {
+    double thr;     // eps / scale
+    int32_t n;
+    __device__ __forceinline__ void two(int32_t, double l1, int32_t, double l2)
+    {
+        n += (l1 > thr) + (l2 > thr);
+    }
+    __device__ __forceinline__ void three(int32_t, double l1, int32_t, double l2, int32_t, double l3)
+    {
+        n += (l1 > thr) + (l2 > thr) + (l3 > thr);
+    }
+};
+
+struct EmitVisit {
+    int32_t* idx;
+    float* len;
+    double thr, scale;
+    int32_t n;
+    __device__ __forceinline__ void one(int32_t I, double l)
+    {
+        if (l > thr) {
+            idx[n] = I;
+            len[n] = (float)(l * scale);
+            ++n;
+        }
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        one(I1, l1);
+        one(I2, l2);
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        one(I1, l1);
+        one(I2, l2);
+        one(I3, l3);
+    }
+};
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
+                                                     float* __restrict__ sino)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.n_rays) return;
+    const int64_t b = blockIdx.y;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+    FwdVisit v{img + b * P.n_units, 0.0};
+    walk<DIM>(P, R, v);
+    sino[b * P.n_rays + r] = (float)(v.acc * R.scale);
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_scatter(DevPlan P, const float* __restrict__ sino,
+                                                     float* img)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.n_rays) return;
+    const int64_t b = blockIdx.y;
+    const float g = sino[b * P.n_rays + r];
+    if (g == 0.0f) return;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+    ScatterVisit v{img + b * P.n_units, (double)g * R.scale};
+    walk<DIM>(P, R, v);
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_counts(DevPlan P, int32_t first, int32_t n, double eps,
+                                                    int32_t* __restrict__ counts)
+{
+    const int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (t >= n) return;
+    Ray R;
+    make_ray<DIM, MODE>(P, first + t, R);
+    CountVisit v{eps / R.scale, 0};
+    walk<DIM>(P, R, v);
+    counts[t] = v.n;
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_hits(DevPlan P, int32_t first, int32_t n, double eps,
+                                                  const int64_t* __restrict__ off,
+                                                  int32_t* __restrict__ idx, float* __restrict__ len)
+{
+    const int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (t >= n) return;
+    Ray R;
+    make_ray<DIM, MODE>(P, first + t, R);
+    const int64_t o = off[t];
+    EmitVisit v{idx + o, len + o, eps / R.scale, R.scale, 0};
+    walk<DIM>(P, R, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(float* __restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = 0.0f;
+}
+
+// Dispatch a kernel template over (dim, mode).
+template <template <int, int> class K, class... Args>
+xrt_status dispatch(const DevPlan& P, dim3 grid, hipStream_t s, Args... args)
+{
+    auto go = [&](auto kern) -> xrt_status {
+        hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, P, args...);
+        return hip_fail(hipGetLastError(), "kernel launch");
+    };
+    if (P.dim == 2) {
+        switch (P.mode) {
+            case MODE_PARALLEL: return go(K<2, MODE_PARALLEL>::fn());
+            case MODE_DIVERGENT: return go(K<2, MODE_DIVERGENT>::fn());
+            case MODE_ARC: return go(K<2, MODE_ARC>::fn());
+            default: return go(K<2, MODE_LIST>::fn());
+        }
+    }
+    switch (P.mode) {
+        case MODE_PARALLEL: return go(K<3, MODE_PARALLEL>::fn());
+        case MODE_DIVERGENT: return go(K<3, MODE_DIVERGENT>::fn());
+        case MODE_ARC: return go(K<3, MODE_ARC>::fn());
+        default: return go(K<3, MODE_LIST>::fn());
+    }
+}
+
+template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M>; } };
+template <int D, int M> struct ScatK { static auto fn() { return k_scatter<D, M>; } };
+template <int D, int M> struct CntK { static auto fn() { return k_counts<D, M>; } };
+template <int D, int M> struct HitK { static auto fn() { return k_hits<D, M>; } };
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return XRT_OK;
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(kBlock), 0, s, dst, n);
+    return hip_fail(hipGetLastError(), "fill kernel launch");
+}
+
+xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    return dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, sino);
+}
+
+xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
+                                  hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    xrt_status st = launch_fill_zero(img, P.n_units * (int64_t)batch, s);
+    if (st != XRT_OK) return st;
+    return dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, img);
+}
+
+xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps, int32_t* counts,
+                             hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    if (n <= 0) return XRT_OK;
+    return dispatch<CntK>(P, dim3(blocks_for(n)), s, (int32_t)first, (int32_t)n, eps, counts);
+}
+
+xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps, const int64_t* offsets,
+                       int32_t* idx, float* len, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    if (n <= 0) return XRT_OK;
+    return dispatch<HitK>(P, dim3(blocks_for(n)), s, (int32_t)first, (int32_t)n, eps, offsets, idx, len);
+}
+
+}  // namespace xrt

@@ -1,0 +1,220 @@
+"""ctypes binding of libxrt.so (include/xrt.h).  Argument marshalling only: every step
+of the transform runs in the library's HIP kernels.  torch provides device memory and
+the stream.  The library must be built (python -m paper_2006_00686_amd.build); there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxrt.so")
+
+KIND = {"par2d": 1, "fan2d_flat": 2, "fan2d_arc": 3, "par3d": 4, "cone_flat": 5, "cone_arc": 6,
+        "raylist2d": 7, "raylist3d": 8}
+ADJ = {"auto": 0, "scatter": 1, "gather": 2}
+
+
+class XrtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib().xrt_status_str(status).decode()} -- "
+                         f"{_lib().xrt_last_error().decode()}")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Scan(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_views", ctypes.c_int32), ("n_rows", ctypes.c_int32),
+                ("n_cols", ctypes.c_int32), ("du", ctypes.c_double), ("dv", ctypes.c_double),
+                ("u0", ctypes.c_double), ("v0", ctypes.c_double), ("sod", ctypes.c_double),
+                ("sdd", ctypes.c_double), ("view_angle", _dp), ("view_z", _dp), ("view_phi2", _dp),
+                ("ray_params", _dp), ("n_rays", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2006_00686_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.xrt_plan_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Scan), ctypes.c_int, ctypes.POINTER(vp)]
+        lib.xrt_plan_destroy.argtypes = [vp]
+        lib.xrt_plan_sizes.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.xrt_forward.argtypes = [vp, vp, vp, i32, vp]
+        lib.xrt_adjoint.argtypes = [vp, vp, vp, i32, i32, vp]
+        lib.xrt_ray_hit_counts.argtypes = [vp, i64, i64, ctypes.c_double, vp, vp]
+        lib.xrt_ray_hits.argtypes = [vp, i64, i64, ctypes.c_double, vp, vp, vp, vp]
+        lib.xrt_status_str.argtypes = [i32]
+        lib.xrt_status_str.restype = ctypes.c_char_p
+        lib.xrt_last_error.restype = ctypes.c_char_p
+        for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
+                  "xrt_ray_hit_counts", "xrt_ray_hits"):
+            getattr(lib, f).restype = ctypes.c_int32
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise XrtError(st, where)
+
+
+def _arr(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+    return a, a.ctypes.data_as(_dp)
+
+
+def _stream(device: int):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Geometry plan: a grid dict and a scan dict (see paper_2006_00686_amd.inputs)."""
+
+    def __init__(self, grid: dict, scan: dict, device: int = 0):
+        lib = _lib()
+        self.grid = dict(grid)
+        self.scan = dict(scan)
+        self.device = int(device)
+        nz = int(grid.get("nz", 0))
+        g = Grid(int(grid["nx"]), int(grid["ny"]), nz, float(grid.get("dx", 1.0)), float(grid.get("dy", 1.0)),
+                 float(grid.get("dz", 1.0)), float(grid.get("cx", 0.0)), float(grid.get("cy", 0.0)),
+                 float(grid.get("cz", 0.0)))
+        kind = scan["kind"]
+        s = Scan()
+        s.kind = KIND[kind]
+        keep = []
+        if kind.startswith("raylist"):
+            w = 2 if kind == "raylist2d" else 4
+            a, p = _arr(scan["rays"])
+            keep.append(a)
+            s.ray_params = p
+            s.n_rays = a.size // w
+            self.sino_shape = (int(s.n_rays),)
+        else:
+            ang, pa = _arr(scan["angles"])
+            keep.append(ang)
+            s.n_views = ang.size
+            s.n_cols = int(scan["ncols"])
+            s.n_rows = int(scan.get("nrows", 1))
+            s.du = float(scan["du"])
+            s.dv = float(scan.get("dv", 1.0))
+            s.u0 = float(scan.get("u0", 0.0))
+            s.v0 = float(scan.get("v0", 0.0))
+            s.sod = float(scan.get("sod", 0.0))
+            s.sdd = float(scan.get("sdd", 0.0))
+            s.view_angle = pa
+            if scan.get("view_z") is not None:
+                z, pz = _arr(scan["view_z"])
+                keep.append(z)
+                s.view_z = pz
+            if scan.get("phi2") is not None:
+                q, pq = _arr(scan["phi2"])
+                keep.append(q)
+                s.view_phi2 = pq
+            if kind in ("par2d", "fan2d_flat", "fan2d_arc"):
+                self.sino_shape = (s.n_views, s.n_cols)
+            else:
+                self.sino_shape = (s.n_views, s.n_rows, s.n_cols)
+        self.image_shape = (int(grid["ny"]), int(grid["nx"])) if nz == 0 else (nz, int(grid["ny"]), int(grid["nx"]))
+        h = ctypes.c_void_p()
+        _check(lib.xrt_plan_create(ctypes.byref(g), ctypes.byref(s), self.device, ctypes.byref(h)),
+               "xrt_plan_create")
+        self._h = h
+        nr, nu = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.xrt_plan_sizes(h, ctypes.byref(nr), ctypes.byref(nu)), "xrt_plan_sizes")
+        self.n_rays, self.n_units = nr.value, nu.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().xrt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -------------------------------------------------------------- operators
+
+    def _batch(self, t: torch.Tensor, inner):
+        n = len(inner)
+        if tuple(t.shape[-n:]) != tuple(inner):
+            raise ValueError(f"expected trailing shape {inner}, got {tuple(t.shape)}")
+        lead = tuple(t.shape[:-n])
+        return lead, int(np.prod(lead)) if lead else 1
+
+    def _dev_check(self, t: torch.Tensor):
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"tensor must live on cuda:{self.device}")
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("tensor must be contiguous float32")
+
+    def forward(self, img: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._dev_check(img)
+        lead, b = self._batch(img, self.image_shape)
+        if out is None:
+            out = torch.empty(lead + tuple(self.sino_shape), dtype=torch.float32, device=img.device)
+        self._dev_check(out)
+        _check(_lib().xrt_forward(self._h, _ptr(img), _ptr(out), b, _stream(self.device)), "xrt_forward")
+        return out
+
+    def adjoint(self, sino: torch.Tensor, mode: str = "auto", out: torch.Tensor | None = None) -> torch.Tensor:
+        self._dev_check(sino)
+        lead, b = self._batch(sino, self.sino_shape)
+        if out is None:
+            out = torch.empty(lead + tuple(self.image_shape), dtype=torch.float32, device=sino.device)
+        self._dev_check(out)
+        _check(_lib().xrt_adjoint(self._h, _ptr(sino), _ptr(out), b, ADJ[mode], _stream(self.device)),
+               "xrt_adjoint")
+        return out
+
+    def hit_counts(self, first: int = 0, n: int | None = None, eps: float = 0.0) -> torch.Tensor:
+        n = self.n_rays - first if n is None else n
+        out = torch.empty(n, dtype=torch.int32, device=f"cuda:{self.device}")
+        _check(_lib().xrt_ray_hit_counts(self._h, first, n, eps, _ptr(out), _stream(self.device)),
+               "xrt_ray_hit_counts")
+        return out
+
+    def hits(self, first: int = 0, n: int | None = None, eps: float = 0.0):
+        """(offsets[n+1], idx, len) CSR of rays [first, first+n), rows in traversal order."""
+        counts = self.hit_counts(first, n, eps)
+        n = counts.numel()
+        offs = torch.zeros(n + 1, dtype=torch.int64, device=counts.device)
+        offs[1:] = torch.cumsum(counts.to(torch.int64), 0)
+        total = int(offs[-1].item())
+        idx = torch.empty(max(total, 1), dtype=torch.int32, device=counts.device)
+        ln = torch.empty(max(total, 1), dtype=torch.float32, device=counts.device)
+        _check(_lib().xrt_ray_hits(self._h, first, n, eps, _ptr(offs), _ptr(idx), _ptr(ln), _stream(self.device)),
+               "xrt_ray_hits")
+        return offs, idx[:total], ln[:total]
