@@ -131,10 +131,10 @@ xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double e
                               int32_t* d_counts, void* stream);
 
 /* Hit lists of rays [first, first+n) (Algorithms 1 and 2: the 1D indices and
- * intersection lengths of each ray).  Row r occupies d_idx/d_len[d_offsets[r] ..
- * d_offsets[r] + count_r), count_r as reported by xrt_ray_hit_counts with the same
- * eps; entries are in order of increasing position along the ray.  d_offsets is
- * int64 [n]. */
+ * intersection lengths of each ray).  d_offsets is an int64 CSR row pointer [n+1]
+ * (normally the exclusive prefix sum of xrt_ray_hit_counts with the same eps); row r
+ * occupies d_idx/d_len[d_offsets[r] .. d_offsets[r+1]) and is filled in order of
+ * increasing position along the ray.  No row writes past d_offsets[r+1]. */
 xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps,
                         const int64_t* d_offsets, int32_t* d_idx, float* d_len, void* stream);
 

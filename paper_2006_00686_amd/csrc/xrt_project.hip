@@ -81,10 +81,10 @@ struct EmitVisit {
     int32_t* idx;
     float* len;
     double thr, scale;
-    int32_t n;
+    int32_t n, cap;
     __device__ __forceinline__ void one(int32_t I, double l)
     {
-        if (l > thr) {
+        if (l > thr && n < cap) {
             idx[n] = I;
             len[n] = (float)(l * scale);
             ++n;
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(DevPlan P, int32_t first, int32
     Ray R;
     make_ray<DIM, MODE>(P, first + t, R);
     const int64_t o = off[t];
-    EmitVisit v{idx + o, len + o, eps / R.scale, R.scale, 0};
+    const int32_t cap = (int32_t)(off[t + 1] - o);
+    EmitVisit v{idx + o, len + o, eps / R.scale, R.scale, 0, cap};
     walk<DIM>(P, R, v);
 }
 
