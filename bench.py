@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--adjoint", default="auto", choices=["auto", "scatter", "gather"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views-every", type=int, default=15)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (this build runs the "
@@ -103,6 +105,12 @@ def main():
     M, V = plan.n_rays, plan.n_units
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
 
+    if args.copy_reference:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         plan.forward(d_img, out=d_sino)
         plan.adjoint(d_sino, mode=args.adjoint, out=d_back)

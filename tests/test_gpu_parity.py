@@ -168,11 +168,15 @@ def test_batched_forward_adjoint(xrt):
 
 def test_rays_missing_the_image(xrt):
     grid = dict(nx=8, ny=8, nz=8)
-    rays = [[20.0, 0.0, 0.3, 0.2], [0.0, 9.0, 1.0, 0.4], [4.0, 0.0, 0.0, 0.0], [0.0, -4.0, 0.0, 0.0]]
+    # far away, beyond the top, on the bottom face y = -4, on the bottom face z = -4
+    # (the half-open rule gives the y = +4 and z = +4 faces to the border units instead)
+    rays = [[20.0, 0.0, 0.3, 0.2], [0.0, 9.0, 1.0, 0.4], [-4.0, 0.0, 0.0, 0.0], [0.0, -4.0, 0.0, 0.0]]
     plan = xrt.Plan(grid, dict(kind="raylist3d", rays=rays))
     got = plan.forward(torch.ones(8, 8, 8, device=dev())).cpu().numpy()
     assert np.all(got == 0)
     assert np.all(plan.hit_counts().cpu().numpy() == 0)
+    on_top = xrt.Plan(grid, dict(kind="raylist3d", rays=[[4.0, 0.0, 0.0, 0.0], [0.0, 4.0, 0.0, 0.0]]))
+    np.testing.assert_array_equal(on_top.forward(torch.ones(8, 8, 8, device=dev())).cpu().numpy(), [8.0, 8.0])
 
 
 def test_geometry_errors_gpu(xrt):
