@@ -32,7 +32,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("xrt_walk.h", "xrt_project.hip", "xrt_internal.h"):
+    for f in ("xrt_walk.h", "xrt_project.hip", "xrt_gather.hip", "xrt_internal.h"):
         with open(os.path.join(ROOT, "paper_2006_00686_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,10 +136,11 @@ def main():
 
     b_fwd = 4.0 * nnz + 4.0 * M        # one 4-byte gather per hit + the ray's output
     b_adj = 4.0 * nnz + 4.0 * V        # one 4-byte operand per hit + the image once
+    adj_kernel = "k_scatter" if args.adjoint == "scatter" else "k_cone_gather"
     if t_fwd >= t_adj:
         kname, bytes_, t_k = "k_forward", b_fwd, t_fwd
     else:
-        kname, bytes_, t_k = "k_scatter", b_adj, t_adj
+        kname, bytes_, t_k = adj_kernel, b_adj, t_adj
     achieved = bytes_ / (t_k * 1e-3) / 1e9
     traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -1,0 +1,209 @@
+// Voxel-driven (gather) adjoint of the X-ray transform for flat-detector cone beams,
+// circular or helical (Secs. 3.2.2-3.2.3), on gfx950.
+//
+// f_I = sum_r g_r len(r, I): every unit sums over the rays that hit it, in a fixed order
+// (deterministic, no atomics).  Rays are enumerated from the unit's shadow on the
+// detector, and each candidate's length is the paper's per-unit condition
+// C_low < C_up, len = C_up - C_low (eqs. conditions_3D_1, range_length_3D), with the
+// interval of every axis taken along the candidate ray.
+//
+// The flat detector is vertical (u horizontal, v along z), so all rays of one detector
+// column c share their projection on the xy plane.  For a voxel column (i, j) and a view,
+// the x and y intervals (the pixel's C_low/C_up in xy) are therefore computed once per
+// column c; each voxel k then only adds the z interval of its 1-3 candidate rows.
+//
+// Work layout: one wavefront per voxel column (i, j) and z chunk, lane = voxel along z,
+// KB voxels per lane.  The sinogram is first transposed to [view][col][row] and scaled by
+// |d| (the ray parameter tau runs along d = detector cell - source, len = |d| dtau), so
+// the lanes of a wave read consecutive rows of one column.
+#include "xrt_walk.h"
+
+namespace xrt {
+namespace {
+
+constexpr int kTile = 32;
+constexpr int kBlock = 256;
+
+// gT[v][c][r] = g[v][r][c] * |d_{c,r}|, |d|^2 = sdd^2 + u_c^2 + v_r^2 (orthogonal frame).
+__global__ __launch_bounds__(kBlock) void k_cone_sino_prep(DevPlan P, const float* __restrict__ g,
+                                                           float* __restrict__ gT, int32_t rblocks)
+{
+    __shared__ float tile[kTile][kTile + 1];
+    const int32_t v = blockIdx.y / rblocks;
+    const int32_t r0 = (blockIdx.y - v * rblocks) * kTile;
+    const int32_t c0 = blockIdx.x * kTile;
+    const int32_t tx = threadIdx.x & (kTile - 1), ty = threadIdx.x >> 5;
+    const double sdd2 = P.sdd * P.sdd;
+    for (int32_t yy = ty; yy < kTile; yy += kBlock / kTile) {
+        const int32_t r = r0 + yy, c = c0 + tx;
+        if (r < P.n_rows && c < P.n_cols) {
+            const double u = fma((double)c, P.du, P.ubase);
+            const double w = fma((double)r, P.dv, P.vbase);
+            const float x = g[((int64_t)v * P.n_rows + r) * P.n_cols + c];
+            tile[yy][tx] = (float)((double)x * sqrt(sdd2 + u * u + w * w));
+        }
+    }
+    __syncthreads();
+    for (int32_t yy = ty; yy < kTile; yy += kBlock / kTile) {
+        const int32_t c = c0 + yy, r = r0 + tx;
+        if (r < P.n_rows && c < P.n_cols) gT[((int64_t)v * P.n_cols + c) * P.n_rows + r] = tile[tx][yy];
+    }
+}
+
+// floor/ceil of x as an index clamped to [-1, hi] (no out-of-range conversion).
+__device__ __forceinline__ int32_t ifloor(double x, int32_t hi)
+{
+    return (int32_t)floor(fmin(fmax(x, -1.0), (double)hi));
+}
+__device__ __forceinline__ int32_t iceil(double x, int32_t hi)
+{
+    return (int32_t)ceil(fmin(fmax(x, -1.0), (double)hi));
+}
+
+// Interval of the ray parameter inside [lo, hi) (half_open_low) or (lo, hi] along one
+// axis, for a ray s + tau*d; an axis the ray does not move along is a membership test.
+__device__ __forceinline__ void axis_interval(double s, double d, double lo, double hi, bool bigger_low,
+                                              double& tin, double& tout)
+{
+    if (d != 0.0) {
+        const double t0 = (lo - s) / d, t1 = (hi - s) / d;
+        tin = fmax(tin, fmin(t0, t1));
+        tout = fmin(tout, fmax(t0, t1));
+    } else {
+        const bool in = bigger_low ? (s >= lo && s < hi) : (s > lo && s <= hi);
+        if (!in) tout = -kInf;
+    }
+}
+
+template <int KB>
+__global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
+                                                         float* __restrict__ img,
+                                                         const double* __restrict__ inv_v, int32_t zero_row,
+                                                         int32_t nzc, int32_t nlogical)
+{
+    // XCD-aware order: hardware block b runs on XCD b % 8; each XCD gets a contiguous
+    // range of logical blocks, so neighbouring voxel columns (whose shadows overlap)
+    // share that XCD's L2.
+    const int32_t per = (int32_t)(gridDim.x >> 3);
+    const int32_t L = (int32_t)(blockIdx.x & 7) * per + (int32_t)(blockIdx.x >> 3);
+    if (L >= nlogical) return;
+    const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t colid = (int64_t)L * (kBlock / 64) + wave;
+    if (colid >= (int64_t)P.nx * P.ny * nzc) return;
+    const int32_t zc = (int32_t)(colid % nzc);
+    const int64_t ij = colid / nzc;
+    const int32_t i = (int32_t)(ij % P.nx), j = (int32_t)(ij / P.nx);
+
+    // unit (k, j, i): x in [xa, xb), y in (ya, yb], z in (za, zb]  (Sec. 4.1 resolution)
+    const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
+    const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
+    const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
+    const int32_t kbase = zc * 64 * KB + lane;
+
+    double acc[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) acc[q] = 0.0;
+
+    for (int32_t v = 0; v < P.n_views; ++v) {
+        const ViewGeom& V = P.views[v];
+        const double Sx = V.A[0], Sy = V.A[1], Sz = V.A[2];
+        const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
+        // detector columns whose rays can cross the pixel: u of the four corners seen
+        // from the source, u = sdd^2 ((P - S).B) / ((P - S).E)
+        double umin = kInf, umax = -kInf;
+#pragma unroll
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const double px = ((cnr & 1) ? xb : xa) - Sx, py = ((cnr & 2) ? yb : ya) - Sy;
+            const double u = sdd2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+        const int32_t c0 = max(iceil((umin - P.ubase) * idu, P.n_cols), 0);
+        const int32_t c1 = min(ifloor((umax - P.ubase) * idu, P.n_cols), P.n_cols - 1);
+        for (int32_t c = c0; c <= c1; ++c) {
+            const double u = fma((double)c, P.du, P.ubase);
+            const double dx = fma(u, Bx, Ex), dy = fma(u, By, Ey);
+            // C_low / C_up of the pixel in xy for every ray of column c
+            double tin = -kInf, tout = kInf;
+            axis_interval(Sx, dx, xa, xb, true, tin, tout);
+            axis_interval(Sy, dy, ya, yb, false, tin, tout);
+            if (!(tin < tout)) continue;
+            const double itin = 1.0 / tin, itout = 1.0 / tout;
+            const float* __restrict__ gcol = gT + ((int64_t)v * P.n_cols + c) * P.n_rows;
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int32_t k = kbase + 64 * q;
+                if (k < P.nz) {
+                    const double zb = P.pz0 - (double)k * P.pdz, za = zb - P.pdz;
+                    const double rel0 = za - Sz, rel1 = zb - Sz;
+                    // rows whose ray has z(tau) = Sz + tau v in (za, zb] for some tau in
+                    // (tin, tout)
+                    const double vlo = fmin(rel0 * itin, rel0 * itout);
+                    const double vhi = fmax(rel1 * itin, rel1 * itout);
+                    const int32_t r0 = max(iceil((vlo - P.vbase) * idv, P.n_rows), 0);
+                    const int32_t r1 = min(ifloor((vhi - P.vbase) * idv, P.n_rows), P.n_rows - 1);
+                    for (int32_t r = r0; r <= r1; ++r) {
+                        double lo = tin, hi = tout;
+                        if (r != zero_row) {
+                            const double iv = inv_v[r];
+                            const double t0 = rel0 * iv, t1 = rel1 * iv;
+                            lo = fmax(lo, fmin(t0, t1));
+                            hi = fmin(hi, fmax(t0, t1));
+                        } else if (!(Sz > za && Sz <= zb)) {
+                            hi = lo;
+                        }
+                        const double l = hi - lo;   // C_up - C_low along tau
+                        if (l > 0.0) acc[q] = fma((double)gcol[r], l, acc[q]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+        const int32_t k = kbase + 64 * q;
+        if (k < P.nz) img[((int64_t)k * P.ny + j) * P.nx + i] = (float)acc[q];
+    }
+}
+
+template <int KB>
+xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    const int32_t nzc = (P.nz + 64 * KB - 1) / (64 * KB);
+    const int64_t cols = (int64_t)P.nx * P.ny * nzc;
+    const int64_t nlog = (cols + kBlock / 64 - 1) / (kBlock / 64);
+    if (nlog > INT32_MAX / 2) {
+        set_error("volume too large for the gather adjoint");
+        return XRT_E_SIZE;
+    }
+    const int64_t launched = (nlog + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_cone_gather<KB>, dim3((unsigned)launched), dim3(kBlock), 0, s, P, gT, img,
+                       (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+    return hip_fail(hipGetLastError(), "gather kernel launch");
+}
+
+}  // namespace
+
+xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
+                                      hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    const int32_t rblocks = (P.n_rows + kTile - 1) / kTile;
+    const dim3 pgrid((unsigned)((P.n_cols + kTile - 1) / kTile), (unsigned)(rblocks * P.n_views));
+    for (int b = 0; b < batch; ++b) {
+        hipLaunchKernelGGL(k_cone_sino_prep, pgrid, dim3(kBlock), 0, s, P, sino + (int64_t)b * P.n_rays,
+                           p->d_gT, rblocks);
+        xrt_status st = hip_fail(hipGetLastError(), "sinogram prep launch");
+        if (st != XRT_OK) return st;
+        float* out = img + (int64_t)b * P.n_units;
+        if (P.nz <= 64) st = launch_kb<1>(p, p->d_gT, out, s);
+        else if (P.nz <= 128) st = launch_kb<2>(p, p->d_gT, out, s);
+        else if (P.nz <= 256) st = launch_kb<4>(p, p->d_gT, out, s);
+        else st = launch_kb<8>(p, p->d_gT, out, s);
+        if (st != XRT_OK) return st;
+    }
+    return XRT_OK;
+}
+
+}  // namespace xrt

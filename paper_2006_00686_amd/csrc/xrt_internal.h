@@ -36,6 +36,10 @@ struct DevPlan {
     // direction w = (d_x*ax, -d_y*ay, -d_z*az); unit (k,j,i) = [i,i+1)x[j,j+1)x[k,k+1)
     double ax, bx, ay, by, az, bz;
     double du, ubase, dv, vbase;      // u = c*du + ubase, v = r*dv + vbase
+    double sdd;                       // source-to-detector distance (flat detectors)
+    // physical unit boundaries: x of index plane 0, y of row plane 0 (top), z of layer
+    // plane 0 (top); unit side lengths
+    double px0, py0, pz0, pdx, pdy, pdz;
     const ViewGeom* views;            // [n_views]
     const double* col_cs;             // MODE_ARC: [n_cols][2] (cos, sin) of the column angle
     const double* row_cs;             // MODE_ARC: [n_rows][2]
@@ -52,6 +56,12 @@ struct xrt_plan {
     void* d_row;
     void* d_rays;
     int32_t kind;
+    // voxel-driven cone adjoint (flat detector): per-row 1/v table and a sinogram
+    // workspace [view][col][row] of one batch member, owned by the plan
+    void* d_invwz;
+    float* d_gT;
+    int32_t zero_row;   // index of a row with v = 0 (ray in a z plane), or -1
+    int32_t gather_ok;  // every unit lies in front of every source position
 };
 
 namespace xrt {
@@ -80,4 +90,7 @@ xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double
 xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps,
                        const int64_t* offsets, int32_t* idx, float* len, hipStream_t s);
 xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s);
+// Voxel-driven gather adjoint for flat-detector cone beams (xrt_gather.hip).
+xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
+                                      hipStream_t s);
 }  // namespace xrt

@@ -310,9 +310,54 @@ xrt_status upload(const std::vector<T>& h, void** d)
 void free_plan(xrt_plan* p)
 {
     if (!p) return;
-    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays})
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT})
         if (q) (void)hipFree(q);
     delete p;
+}
+
+// Tables of the voxel-driven cone adjoint: 1/v of every detector row (v_r is the z
+// component of the row's ray direction) and the transposed-sinogram workspace.
+xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
+{
+    const DevPlan& D = p->dp;
+    p->zero_row = -1;
+    // The detector columns that see a pixel are the interval between its corners' u
+    // coordinates only when the pixel is in front of the source; require it of the
+    // whole image box for every view, otherwise the plan uses the scatter adjoint.
+    p->gather_ok = 1;
+    for (const ViewGeom& V : views) {
+        const double en = std::sqrt(V.E[0] * V.E[0] + V.E[1] * V.E[1] + V.E[2] * V.E[2]);
+        for (int cnr = 0; cnr < 8; ++cnr) {
+            const double P[3] = {D.px0 + ((cnr & 1) ? D.nx * D.pdx : 0.0), D.py0 - ((cnr & 2) ? D.ny * D.pdy : 0.0),
+                                 D.pz0 - ((cnr & 4) ? D.nz * D.pdz : 0.0)};
+            double depth = 0.0;
+            for (int a = 0; a < 3; ++a) depth += (P[a] - V.A[a]) * V.E[a] / en;
+            if (!(depth > 1e-6 * en)) p->gather_ok = 0;
+        }
+    }
+    if (!p->gather_ok) return XRT_OK;
+    std::vector<double> inv((size_t)D.n_rows);
+    for (int r = 0; r < D.n_rows; ++r) {
+        const double v = D.vbase + r * D.dv;
+        if (v == 0.0) {
+            inv[(size_t)r] = 0.0;
+            p->zero_row = r;
+        } else {
+            inv[(size_t)r] = 1.0 / v;
+        }
+    }
+    xrt_status st = upload(inv, &p->d_invwz);
+    if (st != XRT_OK) return st;
+    void* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, (size_t)D.n_rays * sizeof(float));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the %lld-float adjoint workspace failed: %s", (long long)D.n_rays,
+                  hipGetErrorString(e));
+        return XRT_E_NOMEM;
+    }
+    p->d_gT = (float*)ws;
+    return XRT_OK;
 }
 
 }  // namespace
@@ -356,6 +401,13 @@ xrt_status build_tables(const xrt_grid* grid, const xrt_scan* scan, HostTables& 
         D.az = 0.0;
         D.bz = 0.5;
     }
+    D.pdx = g.dx;
+    D.pdy = g.dy;
+    D.pdz = g.nz > 0 ? g.dz : 1.0;
+    D.px0 = g.cx - 0.5 * g.nx * g.dx;
+    D.py0 = g.cy + 0.5 * g.ny * g.dy;
+    D.pz0 = g.nz > 0 ? g.cz + 0.5 * g.nz * g.dz : 0.5;
+    D.sdd = scan->sdd;
     return expand(g, *scan, D, T.views, T.col, T.row, T.rays);
 }
 
@@ -395,6 +447,12 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
     D.col_cs = (const double*)p->d_col;
     D.row_cs = (const double*)p->d_row;
     D.rays = (const double*)p->d_rays;
+    p->zero_row = -1;
+    p->gather_ok = 0;
+    if (p->kind == XRT_CONE_FLAT && (st = cone_gather_setup(p, T.views)) != XRT_OK) {
+        free_plan(p);
+        return st;
+    }
     *out = p;
     return XRT_OK;
 }
@@ -433,11 +491,15 @@ xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_
         set_error("unknown adjoint mode %d", mode);
         return XRT_E_ARG;
     }
-    if (mode == XRT_ADJ_GATHER) {
-        set_error("gather adjoint not available for this plan");
+    const bool has_gather = plan->kind == XRT_CONE_FLAT && plan->gather_ok;
+    if (mode == XRT_ADJ_GATHER && !has_gather) {
+        set_error("the voxel-driven adjoint needs a flat-detector cone scan with the image in front of "
+                  "every source position");
         return XRT_E_UNSUPPORTED;
     }
     DeviceGuard guard(plan->device);
+    if (mode == XRT_ADJ_GATHER || (mode == XRT_ADJ_AUTO && has_gather))
+        return launch_adjoint_cone_gather(plan, d_sino, d_img, batch, (hipStream_t)stream);
     return launch_adjoint_scatter(plan, d_sino, d_img, batch, (hipStream_t)stream);
 }
 

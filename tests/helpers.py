@@ -78,6 +78,11 @@ def small_scans():
     vz = np.linspace(-6, 6, 15)
     out.append(("helical", g3o, dict(kind="cone_flat", angles=np.linspace(0, 3 * 2 * pi, 15, endpoint=False),
                                       ncols=67, nrows=9, du=1.0, dv=1.0, sod=80.0, sdd=120.0, view_z=vz)))
+    # odd row count: the central row has v = 0 and its rays run in the grid plane z = 0
+    # of an even-nz grid (the Sec. 4.1 resolution in 3D); odd column count: u = 0 rays
+    g3e = dict(nx=20, ny=22, nz=16, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0)
+    out.append(("cone_zero_row", g3e, dict(kind="cone_flat", angles=np.arange(8) * (pi / 4), ncols=55,
+                                            nrows=23, du=1.0, dv=1.0, sod=70.0, sdd=105.0)))
     out.append(("cone_arc", g3, dict(kind="cone_arc", angles=np.linspace(0, 2 * pi, 10, endpoint=False),
                                       ncols=65, nrows=21, du=0.006, dv=0.006, sod=90.0,
                                       view_z=np.linspace(-2, 2, 10))))

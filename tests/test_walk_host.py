@@ -25,7 +25,7 @@ PI = math.pi
 
 @pytest.fixture(scope="session")
 def walker(tmp_path_factory):
-    objs = [os.path.join(xbuild.BUILD, o) for o in ("xrt_plan.o", "xrt_project.o")]
+    objs = [os.path.join(xbuild.BUILD, os.path.splitext(src)[0] + ".o") for src in xbuild.SOURCES]
     if not all(os.path.exists(o) for o in objs):
         xbuild.build()
     exe = str(tmp_path_factory.mktemp("walk") / "walk_check")
