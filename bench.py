@@ -101,7 +101,8 @@ def main():
     d_img = torch.from_numpy(img).to(dev)
     d_sino = torch.empty(plan.sino_shape, dtype=torch.float32, device=dev)
     d_back = torch.empty(plan.image_shape, dtype=torch.float32, device=dev)
-    nnz = int(plan.hit_counts().to(torch.int64).sum().item())
+    # hits of physical length > 1e-9 (rays through unit edges leave FP64 slivers of ~1e-13)
+    nnz = int(plan.hit_counts(eps=1e-9).to(torch.int64).sum().item())
     M, V = plan.n_rays, plan.n_units
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
 

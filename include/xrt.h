@@ -46,7 +46,8 @@ typedef enum xrt_status {
     XRT_E_ARG = -1,          /* null pointer, unknown enum value, batch < 1, bad ray range */
     XRT_E_GEOM = -2,         /* invalid geometry: non-positive sizes or spacings, SOD/SDD <= 0,
                                 source inside the image box, non-finite parameters */
-    XRT_E_SIZE = -3,         /* more than 2^31-1 units, or sizes beyond the library's limits */
+    XRT_E_SIZE = -3,         /* more than 2^29-4 units or 2^31-1 rays per image, or sizes beyond
+                                the library's limits */
     XRT_E_HIP = -4,          /* a HIP runtime call failed (see xrt_last_error) */
     XRT_E_NOMEM = -5,        /* device or host allocation failed */
     XRT_E_UNSUPPORTED = -6   /* valid request that this build does not implement */

@@ -97,7 +97,8 @@ xrt_status validate(const xrt_grid* g, const xrt_scan* s)
         return XRT_E_GEOM;
     }
     const int64_t nu = (int64_t)g->nx * g->ny * (g->nz > 0 ? g->nz : 1);
-    if (nu > INT32_MAX) { set_error("more than 2^31-1 units"); return XRT_E_SIZE; }
+    // image byte offsets are 32-bit (buffer loads with hardware bounds checks)
+    if (nu > (int64_t)(INT32_MAX - 15) / 4) { set_error("more than 2^29 - 4 units"); return XRT_E_SIZE; }
     if (is2d(s->kind) != (g->nz == 0)) {
         set_error("scan kind %d does not match a %dD grid", s->kind, g->nz == 0 ? 2 : 3);
         return XRT_E_GEOM;

@@ -12,38 +12,54 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Visitors receive the candidates of one slab.  The first candidate (the unit the ray is
-// in at slab entry) always has a valid index; the others are only valid when their
-// length is positive.
+// Visitors (see walk() for the candidate contract).
 //
-// Forward: the gathers are issued unconditionally, a candidate that is not hit reads the
-// entry unit instead (same cache line, always in range) and is weighted by 0, so the
-// three loads of a slab are in flight together instead of each behind its own branch.
+// Forward: gathers are hardware-bounds-checked buffer loads on byte offsets.  A
+// candidate that is not hit is pointed out of range, so its load returns 0 without a
+// memory access and its (finite) length adds nothing; the loads of a slab are issued
+// together.
+constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
+
+__device__ __forceinline__ const float* uniform_ptr(const float* p)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (const float*)(((uint64_t)hi << 32) | lo);
+}
+
 struct FwdVisit {
-    const float* __restrict__ img;
+    static constexpr int32_t kIndexScale = 4;
+    const float* img;    // wave-uniform base of one image
+    int32_t nbytes;      // wave-uniform size of the image in bytes
     double acc;
+    __device__ __forceinline__ float load(int32_t off)
+    {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)uniform_ptr(img), (short)0, __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
     __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
     {
-        const bool h2 = l2 > 0.0;
-        const float f1 = img[I1];
-        const float f2 = img[h2 ? I2 : I1];
-        acc = fma((double)f1, fmax(l1, 0.0), acc);
-        acc = fma((double)f2, h2 ? l2 : 0.0, acc);
+        const float f1 = load(I1);
+        const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
+        acc = fma((double)f1, l1, acc);
+        acc = fma((double)f2, l2, acc);
     }
     __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
                                           double l3)
     {
-        const bool h2 = l2 > 0.0, h3 = l3 > 0.0;
-        const float f1 = img[I1];
-        const float f2 = img[h2 ? I2 : I1];
-        const float f3 = img[h3 ? I3 : I1];
-        acc = fma((double)f1, fmax(l1, 0.0), acc);
-        acc = fma((double)f2, h2 ? l2 : 0.0, acc);
-        acc = fma((double)f3, h3 ? l3 : 0.0, acc);
+        const float f1 = load(I1);
+        const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
+        const float f3 = load(l3 > 0.0 ? I3 : kOutOfRange);
+        acc = fma((double)f1, l1, acc);
+        acc = fma((double)f2, l2, acc);
+        acc = fma((double)f3, l3, acc);
     }
 };
 
 struct ScatterVisit {
+    static constexpr int32_t kIndexScale = 1;
     float* img;
     double gw;
     __device__ __forceinline__ void one(int32_t I, double l)
@@ -65,6 +81,7 @@ struct ScatterVisit {
 };
 
 struct CountVisit {
+    static constexpr int32_t kIndexScale = 1;
     double thr;     // eps / scale
     int32_t n;
     __device__ __forceinline__ void two(int32_t, double l1, int32_t, double l2)
@@ -78,6 +95,7 @@ struct CountVisit {
 };
 
 struct EmitVisit {
+    static constexpr int32_t kIndexScale = 1;
     int32_t* idx;
     float* len;
     double thr, scale;
@@ -113,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __re
     const int64_t b = blockIdx.y;
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
-    FwdVisit v{img + b * P.n_units, 0.0};
+    FwdVisit v{img + b * P.n_units, (int32_t)(P.n_units * 4), 0.0};
     walk<DIM>(P, R, v);
     sino[b * P.n_rays + r] = (float)(v.acc * R.scale);
 }

@@ -185,62 +185,73 @@ XRT_HD bool setup_axes(const DevPlan& P, const Ray& R, Axis* ax,
     return true;
 }
 
-// Walk the chord slab by slab; the visitor gets every candidate unit of a slab with
-// len = C_up - C_low in ray-parameter units (<= 0: not a hit).
+// Walk the chord slab by slab.  The visitor receives the candidate units of every slab
+// with their C_up - C_low in ray-parameter units: vis.two(I1, l1, I2, l2) (2D) or
+// vis.three(I1, l1, I2, l2, I3, l3) (3D), where I1 -- the unit the ray is in at slab
+// entry -- is always a valid unit with l1 >= 0, and I2, I3 are valid units only when
+// their length is positive (<= 0: not a hit; always finite).  Indices are in units of
+// Visit::kIndexScale (1: element index, 4: byte offset).
+//
+// The first slab and the last two are walked with the exact per-slab expressions (every
+// crossing parameter is (plane - q) / w, the expression of the box clip, so no face of
+// the box is crossed before the chord ends).  The slabs in between keep, per secondary
+// axis, the distance r from the slab start to the next crossing and step it by the slab
+// width dt0 (a DDA in the ray parameter): two fewer exact evaluations per slab and no
+// bounds logic, which the one-slab margin to the chord's end makes unnecessary.
 template <int DIM, class Visit>
 XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
 {
+    constexpr double kNone = 1e300;   // "no further crossing" (finite: 0 * l stays 0)
     Axis ax[3];
     double tin, tout;
     if (!setup_axes<DIM>(P, R, ax, tin, tout)) return;
+    constexpr int32_t SC = Visit::kIndexScale;
 
     int32_t I = 0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) I += ax[a].idx * ax[a].st;
-    const int32_t sd0 = (int32_t)ax[0].sg * ax[0].st;
-    const int32_t sd1 = (int32_t)ax[1].sg * ax[1].st;
-    const double dt0 = fabs(ax[0].inv);
-    double tn0 = ax[0].tn;
-    double tn1 = ax[1].tn, m1 = ax[1].m;
+    for (int a = 0; a < DIM; ++a) I += ax[a].idx * ax[a].st * SC;
+    const int32_t sd0 = (int32_t)ax[0].sg * ax[0].st * SC;
+    const int32_t sd1 = (int32_t)ax[1].sg * ax[1].st * SC;
+    const double q0 = ax[0].q, inv0 = ax[0].inv, sg0 = ax[0].sg, dt0 = fabs(ax[0].inv);
+    double m0 = ax[0].m;   // index of the driving plane that ends the current slab
     const double q1 = ax[1].q, inv1 = ax[1].inv, sg1 = ax[1].sg;
+    double m1 = ax[1].m, tn1 = ax[1].w != 0.0 ? ax[1].tn : kNone;
+    double q2 = 0.0, inv2 = 0.0, sg2 = 0.0, m2 = 0.0, tn2 = kNone;
+    int32_t sd2 = 0;
+    if constexpr (DIM == 3) {
+        q2 = ax[2].q;
+        inv2 = ax[2].inv;
+        sg2 = ax[2].sg;
+        m2 = ax[2].m;
+        tn2 = ax[2].w != 0.0 ? ax[2].tn : kNone;
+        sd2 = (int32_t)ax[2].sg * ax[2].st * SC;
+    }
     double tx0 = tin;
     const int32_t nslab = ax[0].ncr + 1;
 
-    if constexpr (DIM == 2) {
-        for (int32_t s = nslab; s > 0; --s) {
-            const double tx1 = (s == 1) ? tout : fmin(tn0, tout);
-            // candidates j (entry row) and j + sg1 (after the crossing at tn1)
-            const double l1 = fmin(tx1, tn1) - tx0;   // C_up - C_low of the entry unit
-            const double l2 = tx1 - tn1;              // C_up - C_low of the next unit
+    // one slab with the exact expressions
+    auto exact_slab = [&](bool last) {
+        const double tx1 = last ? tout : fmin(plane_t(m0, ax[0]), tout);
+        if constexpr (DIM == 2) {
+            const double l1 = fmin(tx1, tn1) - tx0;
+            const double l2 = tx1 - tn1;
             const bool c1 = tn1 < tx1;
             const int32_t Iend = c1 ? I + sd1 : I;
-            vis.two(I, l1, Iend, l2);
+            vis.two(I, fmax(l1, 0.0), Iend, l2);
             if (c1) {
                 m1 += sg1;
                 tn1 = (m1 - q1) * inv1;
             }
             I = Iend + sd0;
-            tn0 += dt0;
-            tx0 = tx1;
-        }
-    } else {
-        const int32_t sd2 = (int32_t)ax[2].sg * ax[2].st;
-        double tn2 = ax[2].tn, m2 = ax[2].m;
-        const double q2 = ax[2].q, inv2 = ax[2].inv, sg2 = ax[2].sg;
-        for (int32_t s = nslab; s > 0; --s) {
-            const double tx1 = (s == 1) ? tout : fmin(tn0, tout);
-            // candidates (j,k), (j',k) or (j,k'), (j',k'): at most three of the four
-            // range pairs can be hit by a line inside one slab
-            const double a = fmin(tn1, tn2);
-            const double b = fmax(tn1, tn2);
+        } else {
+            const double a = fmin(tn1, tn2), b = fmax(tn1, tn2);
             const double l1 = fmin(tx1, a) - tx0;
             const double l2 = fmin(tx1, b) - a;
             const double l3 = tx1 - b;
-            const bool c1 = tn1 < tx1;
-            const bool c2 = tn2 < tx1;
+            const bool c1 = tn1 < tx1, c2 = tn2 < tx1;
             const int32_t Imid = I + (tn1 < tn2 ? sd1 : sd2);
             const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
-            vis.three(I, l1, Imid, l2, Iend, l3);
+            vis.three(I, fmax(l1, 0.0), Imid, l2, Iend, l3);
             if (c1) {
                 m1 += sg1;
                 tn1 = (m1 - q1) * inv1;
@@ -250,10 +261,65 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                 tn2 = (m2 - q2) * inv2;
             }
             I = Iend + sd0;
-            tn0 += dt0;
-            tx0 = tx1;
         }
+        m0 += sg0;
+        tx0 = tx1;
+    };
+
+    exact_slab(nslab == 1);
+    int32_t left = nslab - 1;
+    if (left > 2) {
+        const int32_t nint = left - 2;
+        const double dt1 = ax[1].w != 0.0 ? fabs(inv1) : kNone;
+        const double e1 = dt1 - dt0;
+        double r1 = fmax(tn1 - tx0, 0.0);
+        int32_t n1 = 0;
+        if constexpr (DIM == 2) {
+            for (int32_t s = nint; s > 0; --s) {
+                const double l1 = fmin(r1, dt0);
+                const double l2 = dt0 - r1;
+                const bool c1 = r1 < dt0;
+                const int32_t Iend = c1 ? I + sd1 : I;
+                vis.two(I, l1, Iend, l2);
+                n1 += c1;
+                r1 += c1 ? e1 : -dt0;
+                I = Iend + sd0;
+            }
+        } else {
+            const double dt2 = ax[2].w != 0.0 ? fabs(inv2) : kNone;
+            const double e2 = dt2 - dt0;
+            double r2 = fmax(tn2 - tx0, 0.0);
+            int32_t n2 = 0;
+            for (int32_t s = nint; s > 0; --s) {
+                const double a = fmin(r1, r2), b = fmax(r1, r2);
+                const double l1 = fmin(a, dt0);
+                const double l2 = fmin(b, dt0) - a;
+                const double l3 = dt0 - b;
+                const bool c1 = r1 < dt0, c2 = r2 < dt0;
+                const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
+                const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
+                vis.three(I, l1, Imid, l2, Iend, l3);
+                n1 += c1;
+                n2 += c2;
+                r1 += c1 ? e1 : -dt0;
+                r2 += c2 ? e2 : -dt0;
+                I = Iend + sd0;
+            }
+            if (n2 > 0) {
+                m2 += sg2 * (double)n2;
+                tn2 = (m2 - q2) * inv2;
+            }
+        }
+        if (n1 > 0) {
+            m1 += sg1 * (double)n1;
+            tn1 = (m1 - q1) * inv1;
+        }
+        // back to the exact parameters at the start of the next slab
+        tx0 = (m0 + sg0 * (double)(nint - 1) - q0) * inv0;
+        m0 += sg0 * (double)nint;
+        left = 2;
     }
+    for (; left > 0; --left) exact_slab(left == 1);
 }
 
 }  // namespace xrt

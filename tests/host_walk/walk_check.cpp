@@ -8,6 +8,7 @@
 //            parameters as whitespace-separated numbers.
 // hits.bin: per ray int32 count, then count x (int32 index, float64 length).
 #include <cstdio>
+#include <cmath>
 #include <cstdlib>
 #include <vector>
 
@@ -18,6 +19,7 @@ using namespace xrt;
 namespace {
 
 struct CheckVisit {
+    static constexpr int32_t kIndexScale = 1;
     int64_t n_units;
     double thr, scale;
     std::vector<int32_t> idx;
@@ -29,15 +31,23 @@ struct CheckVisit {
         if (l > 0.0) check(I);
         if (l > thr) { idx.push_back(I); len.push_back(l * scale); }
     }
+    // contract of walk(): I1 always valid with l1 >= 0; every length finite
+    void first(int32_t I1, double l1)
+    {
+        check(I1);
+        if (!(l1 >= 0.0)) ++bad;
+    }
     void two(int32_t I1, double l1, int32_t I2, double l2)
     {
-        check(I1);   // always loaded by the forward kernel
+        first(I1, l1);
+        if (!std::isfinite(l2)) ++bad;
         one(I1, l1);
         one(I2, l2);
     }
     void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3, double l3)
     {
-        check(I1);
+        first(I1, l1);
+        if (!std::isfinite(l2) || !std::isfinite(l3)) ++bad;
         one(I1, l1);
         one(I2, l2);
         one(I3, l3);
@@ -123,6 +133,6 @@ int main(int argc, char** argv)
     if (!out) return 2;
     long bad = T.dp.dim == 2 ? run_dim<2>(T.dp, eps, out) : run_dim<3>(T.dp, eps, out);
     fclose(out);
-    if (bad) { fprintf(stderr, "%ld out-of-range image indices\n", bad); return 3; }
+    if (bad) { fprintf(stderr, "%ld out-of-range image indices or contract violations\n", bad); return 3; }
     return 0;
 }
