@@ -60,22 +60,49 @@ __device__ __forceinline__ int32_t iceil(double x, int32_t hi)
     return (int32_t)ceil(fmin(fmax(x, -1.0), (double)hi));
 }
 
-// Interval of the ray parameter inside [lo, hi) (half_open_low) or (lo, hi] along one
-// axis, for a ray s + tau*d; an axis the ray does not move along is a membership test.
-__device__ __forceinline__ void axis_interval(double s, double d, double lo, double hi, bool bigger_low,
-                                              double& tin, double& tout)
+// 1/x: hardware estimate refined by one Newton step (full FP64 precision for the
+// lengths; the ranges below only need the estimate).
+__device__ __forceinline__ double rcp_fast(double x)
+{
+    return __builtin_amdgcn_rcp(x);
+}
+__device__ __forceinline__ double rcp_full(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Interval of the ray parameter inside one axis slab, for a ray s + tau*d whose
+// offsets to the slab faces are a0 = lo - s, a1 = hi - s; a ray that does not move
+// along the axis is in the slab iff the unit owns its coordinate (half-open faces).
+__device__ __forceinline__ void axis_interval(double a0, double a1, double d, bool bigger_low, double& tin,
+                                              double& tout)
 {
     if (d != 0.0) {
-        const double t0 = (lo - s) / d, t1 = (hi - s) / d;
+        const double id = rcp_full(d);
+        const double t0 = a0 * id, t1 = a1 * id;
         tin = fmax(tin, fmin(t0, t1));
         tout = fmin(tout, fmax(t0, t1));
     } else {
-        const bool in = bigger_low ? (s >= lo && s < hi) : (s > lo && s <= hi);
+        // a0 <= 0 < a1: s in [lo, hi);  a0 < 0 <= a1: s in (lo, hi]
+        const bool in = bigger_low ? (a0 <= 0.0 && a1 > 0.0) : (a0 < 0.0 && a1 >= 0.0);
         if (!in) tout = -kInf;
     }
 }
 
-template <int KB>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t bytes)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
+                                             __builtin_amdgcn_readfirstlane((int32_t)bytes), 0x00020000);
+}
+
+constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
+constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
+
+template <int KB, int NR>
 __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
                                                          float* __restrict__ img,
                                                          const double* __restrict__ inv_v, int32_t zero_row,
@@ -99,62 +126,77 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
     const int32_t kbase = zc * 64 * KB + lane;
+    const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, P.n_rays * 4);
 
-    double acc[KB];
+    double acc[KB], zb0[KB];
 #pragma unroll
-    for (int q = 0; q < KB; ++q) acc[q] = 0.0;
+    for (int q = 0; q < KB; ++q) {
+        acc[q] = 0.0;
+        zb0[q] = P.pz0 - (double)(kbase + 64 * q) * P.pdz;   // top face of the lane's voxel q
+    }
 
     for (int32_t v = 0; v < P.n_views; ++v) {
         const ViewGeom& V = P.views[v];
         const double Sx = V.A[0], Sy = V.A[1], Sz = V.A[2];
         const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
+        const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
         // detector columns whose rays can cross the pixel: u of the four corners seen
         // from the source, u = sdd^2 ((P - S).B) / ((P - S).E)
         double umin = kInf, umax = -kInf;
 #pragma unroll
         for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = ((cnr & 1) ? xb : xa) - Sx, py = ((cnr & 2) ? yb : ya) - Sy;
-            const double u = sdd2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+            const double px = (cnr & 1) ? ax1 : ax0, py = (cnr & 2) ? ay1 : ay0;
+            const double u = sdd2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
             umin = fmin(umin, u);
             umax = fmax(umax, u);
         }
-        const int32_t c0 = max(iceil((umin - P.ubase) * idu, P.n_cols), 0);
-        const int32_t c1 = min(ifloor((umax - P.ubase) * idu, P.n_cols), P.n_cols - 1);
+        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
+        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
         for (int32_t c = c0; c <= c1; ++c) {
             const double u = fma((double)c, P.du, P.ubase);
-            const double dx = fma(u, Bx, Ex), dy = fma(u, By, Ey);
-            // C_low / C_up of the pixel in xy for every ray of column c
+            // C_low / C_up of the pixel in xy, shared by every ray of column c
             double tin = -kInf, tout = kInf;
-            axis_interval(Sx, dx, xa, xb, true, tin, tout);
-            axis_interval(Sy, dy, ya, yb, false, tin, tout);
+            axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
+            axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
             if (!(tin < tout)) continue;
-            const double itin = 1.0 / tin, itout = 1.0 / tout;
-            const float* __restrict__ gcol = gT + ((int64_t)v * P.n_cols + c) * P.n_rows;
+            // rows: z(tau) = Sz + tau v crosses (za, zb] for some tau in (tin, tout);
+            // v = rel / tau, scaled to bin units
+            const double sin_ = rcp_fast(tin) * idv, sout = rcp_fast(tout) * idv;
+            const double vb = -P.vbase * idv;
+            const int32_t gcol = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows);
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
                 const int32_t k = kbase + 64 * q;
                 if (k < P.nz) {
-                    const double zb = P.pz0 - (double)k * P.pdz, za = zb - P.pdz;
-                    const double rel0 = za - Sz, rel1 = zb - Sz;
-                    // rows whose ray has z(tau) = Sz + tau v in (za, zb] for some tau in
-                    // (tin, tout)
-                    const double vlo = fmin(rel0 * itin, rel0 * itout);
-                    const double vhi = fmax(rel1 * itin, rel1 * itout);
-                    const int32_t r0 = max(iceil((vlo - P.vbase) * idv, P.n_rows), 0);
-                    const int32_t r1 = min(ifloor((vhi - P.vbase) * idv, P.n_rows), P.n_rows - 1);
-                    for (int32_t r = r0; r <= r1; ++r) {
+                    const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
+                    const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
+                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                    const int32_t r0 = max(iceil(vlo - kRangeSlack, P.n_rows), 0);
+                    const int32_t r1 = min(ifloor(vhi + kRangeSlack, P.n_rows), P.n_rows - 1);
+                    // at most NR rows: the plan bounds the height of a voxel's shadow
+                    // (in bins) below NR - 1; the NR loads go out together
+                    float gv[NR];
+                    double lv[NR];
+#pragma unroll
+                    for (int e = 0; e < NR; ++e) {
+                        const int32_t r = r0 + e;
+                        const double vr = fma((double)r, P.dv, P.vbase);
                         double lo = tin, hi = tout;
                         if (r != zero_row) {
-                            const double iv = inv_v[r];
+                            const double iv = rcp_full(vr);
                             const double t0 = rel0 * iv, t1 = rel1 * iv;
                             lo = fmax(lo, fmin(t0, t1));
                             hi = fmin(hi, fmax(t0, t1));
-                        } else if (!(Sz > za && Sz <= zb)) {
-                            hi = lo;
+                        } else if (!(rel0 < 0.0 && rel1 >= 0.0)) {
+                            hi = lo;   // the ray's plane z = Sz is not in (za, zb]
                         }
-                        const double l = hi - lo;   // C_up - C_low along tau
-                        if (l > 0.0) acc[q] = fma((double)gcol[r], l, acc[q]);
+                        const bool hit = r <= r1 && hi > lo;   // C_low < C_up
+                        lv[e] = hit ? hi - lo : 0.0;
+                        gv[e] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(gsrc, hit ? (gcol + r) * 4 : kOutOfRange, 0, 0));
                     }
+#pragma unroll
+                    for (int e = 0; e < NR; ++e) acc[q] = fma((double)gv[e], lv[e], acc[q]);
                 }
             }
         }
@@ -166,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
     }
 }
 
-template <int KB>
+template <int KB, int NR>
 xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
 {
     const DevPlan& P = p->dp;
@@ -178,9 +220,19 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
         return XRT_E_SIZE;
     }
     const int64_t launched = (nlog + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_cone_gather<KB>, dim3((unsigned)launched), dim3(kBlock), 0, s, P, gT, img,
+    hipLaunchKernelGGL((k_cone_gather<KB, NR>), dim3((unsigned)launched), dim3(kBlock), 0, s, P, gT, img,
                        (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
     return hip_fail(hipGetLastError(), "gather kernel launch");
+}
+
+template <int NR>
+xrt_status launch_nr(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
+{
+    const int32_t nz = p->dp.nz;
+    if (nz <= 64) return launch_kb<1, NR>(p, gT, img, s);
+    if (nz <= 128) return launch_kb<2, NR>(p, gT, img, s);
+    if (nz <= 256) return launch_kb<4, NR>(p, gT, img, s);
+    return launch_kb<8, NR>(p, gT, img, s);
 }
 
 }  // namespace
@@ -197,10 +249,9 @@ xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, floa
         xrt_status st = hip_fail(hipGetLastError(), "sinogram prep launch");
         if (st != XRT_OK) return st;
         float* out = img + (int64_t)b * P.n_units;
-        if (P.nz <= 64) st = launch_kb<1>(p, p->d_gT, out, s);
-        else if (P.nz <= 128) st = launch_kb<2>(p, p->d_gT, out, s);
-        else if (P.nz <= 256) st = launch_kb<4>(p, p->d_gT, out, s);
-        else st = launch_kb<8>(p, p->d_gT, out, s);
+        if (p->gather_nr <= 2) st = launch_nr<2>(p, p->d_gT, out, s);
+        else if (p->gather_nr == 3) st = launch_nr<3>(p, p->d_gT, out, s);
+        else st = launch_nr<4>(p, p->d_gT, out, s);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;

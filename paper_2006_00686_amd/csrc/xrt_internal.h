@@ -62,6 +62,7 @@ struct xrt_plan {
     float* d_gT;
     int32_t zero_row;   // index of a row with v = 0 (ray in a z plane), or -1
     int32_t gather_ok;  // every unit lies in front of every source position
+    int32_t gather_nr;  // bound on the detector rows one voxel's shadow covers per column
 };
 
 namespace xrt {

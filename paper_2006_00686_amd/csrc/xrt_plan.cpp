@@ -325,7 +325,8 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
     // The detector columns that see a pixel are the interval between its corners' u
     // coordinates only when the pixel is in front of the source; require it of the
     // whole image box for every view, otherwise the plan uses the scatter adjoint.
-    p->gather_ok = 1;
+    // sinogram byte offsets are 32-bit in the gather kernel
+    p->gather_ok = D.n_rays <= (int64_t)(INT32_MAX - 15) / 4 ? 1 : 0;
     for (const ViewGeom& V : views) {
         const double en = std::sqrt(V.E[0] * V.E[0] + V.E[1] * V.E[1] + V.E[2] * V.E[2]);
         for (int cnr = 0; cnr < 8; ++cnr) {
@@ -337,6 +338,32 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
         }
     }
     if (!p->gather_ok) return XRT_OK;
+    // Bound on the rows whose rays can cross one voxel, for one detector column.  Along
+    // a column the horizontal distance h from the source and the ray parameter satisfy
+    // tau = h / rho with rho = |E + u B| <= sqrt(sdd^2 + u_max^2); a voxel's rows have
+    // v = (z - Sz)/tau over its z range and the pixel's h interval [h_in, h_in + diag],
+    // so their spread is at most rho (dz / h_min + |z - Sz|_max diag / h_min^2).
+    {
+        const double umax = std::fabs(D.ubase) + (D.n_cols - 1) * D.du;
+        const double rho = std::sqrt(D.sdd * D.sdd + umax * umax);
+        const double bx0 = D.px0, bx1 = D.px0 + D.nx * D.pdx, by1 = D.py0, by0 = D.py0 - D.ny * D.pdy;
+        const double zhi = D.pz0, zlo = D.pz0 - D.nz * D.pdz;
+        double hmin = INFINITY, zrel = 0.0;
+        for (const ViewGeom& V : views) {
+            const double ddx = std::fmax(std::fmax(bx0 - V.A[0], V.A[0] - bx1), 0.0);
+            const double ddy = std::fmax(std::fmax(by0 - V.A[1], V.A[1] - by1), 0.0);
+            hmin = std::fmin(hmin, std::sqrt(ddx * ddx + ddy * ddy));
+            zrel = std::fmax(zrel, std::fmax(std::fabs(zhi - V.A[2]), std::fabs(zlo - V.A[2])));
+        }
+        const double diag = std::sqrt(D.pdx * D.pdx + D.pdy * D.pdy);
+        const double spread = rho * (D.pdz / hmin + zrel * diag / (hmin * hmin)) / D.dv;
+        const double nr = std::floor(spread + 1e-6) + 1.0;
+        if (!(hmin > 0.0) || !(nr <= 4.0)) {
+            p->gather_ok = 0;
+            return XRT_OK;
+        }
+        p->gather_nr = (int32_t)nr;
+    }
     std::vector<double> inv((size_t)D.n_rows);
     for (int r = 0; r < D.n_rows; ++r) {
         const double v = D.vbase + r * D.dv;
