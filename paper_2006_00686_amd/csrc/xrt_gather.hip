@@ -102,12 +102,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64
 constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
 constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
 
-template <int KB, int NR>
+// One wave per voxel column (i, j) and z chunk; lane = voxel along z, KB per lane.
+// NR: bound on the rows a voxel's shadow covers in one detector column (from the plan).
+// ZR: the detector has a row with v = 0, whose rays lie in the plane z = Sz.
+template <int KB, int NR, bool ZR>
 __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
                                                          float* __restrict__ img,
                                                          const double* __restrict__ inv_v, int32_t zero_row,
                                                          int32_t nzc, int32_t nlogical)
 {
+    // 1/v of every row, followed by NR entries 0 for rows past the detector: their z
+    // interval (0, 0) lies before tin > 0, so they are never hit
+    extern __shared__ double s_iv[];
+    for (int32_t r = threadIdx.x; r < P.n_rows + NR; r += kBlock) s_iv[r] = r < P.n_rows ? inv_v[r] : 0.0;
+    __syncthreads();
+
     // XCD-aware order: hardware block b runs on XCD b % 8; each XCD gets a contiguous
     // range of logical blocks, so neighbouring voxel columns (whose shadows overlap)
     // share that XCD's L2.
@@ -159,44 +168,53 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
             axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
             axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
             if (!(tin < tout)) continue;
-            // rows: z(tau) = Sz + tau v crosses (za, zb] for some tau in (tin, tout);
-            // v = rel / tau, scaled to bin units
+            // first candidate row: the smallest v = rel / tau of the voxel over
+            // tau in (tin, tout), in bin units
             const double sin_ = rcp_fast(tin) * idv, sout = rcp_fast(tout) * idv;
             const double vb = -P.vbase * idv;
-            const int32_t gcol = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows);
+            const int32_t gcol4 = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
                 const int32_t k = kbase + 64 * q;
-                if (k < P.nz) {
-                    const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
-                    const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
-                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                    const int32_t r0 = max(iceil(vlo - kRangeSlack, P.n_rows), 0);
-                    const int32_t r1 = min(ifloor(vhi + kRangeSlack, P.n_rows), P.n_rows - 1);
-                    // at most NR rows: the plan bounds the height of a voxel's shadow
-                    // (in bins) below NR - 1; the NR loads go out together
-                    float gv[NR];
-                    double lv[NR];
-#pragma unroll
-                    for (int e = 0; e < NR; ++e) {
-                        const int32_t r = r0 + e;
-                        const double vr = fma((double)r, P.dv, P.vbase);
-                        double lo = tin, hi = tout;
-                        if (r != zero_row) {
-                            const double iv = rcp_full(vr);
-                            const double t0 = rel0 * iv, t1 = rel1 * iv;
-                            lo = fmax(lo, fmin(t0, t1));
-                            hi = fmin(hi, fmax(t0, t1));
-                        } else if (!(rel0 < 0.0 && rel1 >= 0.0)) {
-                            hi = lo;   // the ray's plane z = Sz is not in (za, zb]
-                        }
-                        const bool hit = r <= r1 && hi > lo;   // C_low < C_up
-                        lv[e] = hit ? hi - lo : 0.0;
-                        gv[e] = __builtin_bit_cast(
-                            float, __builtin_amdgcn_raw_buffer_load_b32(gsrc, hit ? (gcol + r) * 4 : kOutOfRange, 0, 0));
+                const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
+                const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
+                // rows outside the voxel's range fail C_low < C_up below on their own
+                // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
+                const int32_t r0 = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
+                auto row = [&](int e, double& l, float& g) {
+                    const int32_t r = r0 + e;
+                    double lo = tin, hi = tout;
+                    if (ZR && r == zero_row) {
+                        if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
+                    } else {
+                        const double iv = s_iv[r];
+                        const double t0 = rel0 * iv, t1 = rel1 * iv;
+                        lo = fmax(lo, fmin(t0, t1));
+                        hi = fmin(hi, fmax(t0, t1));
                     }
+                    const bool hit = hi > lo && k < P.nz;   // C_low < C_up
+                    l = hit ? hi - lo : 0.0;
+                    g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                      gsrc, hit ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                };
+                double l0, l1;
+                float g0, g1;
+                row(0, l0, g0);
+                row(1, l1, g1);
+                acc[q] = fma((double)g0, l0, acc[q]);
+                acc[q] = fma((double)g1, l1, acc[q]);
+                if constexpr (NR > 2) {
+                    // rarely needed: only where the shadow spans more than one bin
+                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                    if (vhi + kRangeSlack >= (double)(r0 + 2)) {
 #pragma unroll
-                    for (int e = 0; e < NR; ++e) acc[q] = fma((double)gv[e], lv[e], acc[q]);
+                        for (int e = 2; e < NR; ++e) {
+                            double le;
+                            float ge;
+                            row(e, le, ge);
+                            acc[q] = fma((double)ge, le, acc[q]);
+                        }
+                    }
                 }
             }
         }
@@ -220,8 +238,13 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
         return XRT_E_SIZE;
     }
     const int64_t launched = (nlog + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_cone_gather<KB, NR>), dim3((unsigned)launched), dim3(kBlock), 0, s, P, gT, img,
-                       (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+    const size_t lds = (size_t)(P.n_rows + NR) * sizeof(double);
+    if (p->zero_row >= 0)
+        hipLaunchKernelGGL((k_cone_gather<KB, NR, true>), dim3((unsigned)launched), dim3(kBlock), lds, s, P, gT,
+                           img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+    else
+        hipLaunchKernelGGL((k_cone_gather<KB, NR, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P, gT,
+                           img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 

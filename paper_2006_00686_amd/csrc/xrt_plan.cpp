@@ -358,7 +358,8 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
         const double diag = std::sqrt(D.pdx * D.pdx + D.pdy * D.pdy);
         const double spread = rho * (D.pdz / hmin + zrel * diag / (hmin * hmin)) / D.dv;
         const double nr = std::floor(spread + 1e-6) + 1.0;
-        if (!(hmin > 0.0) || !(nr <= 4.0)) {
+        // the 1/v table of the rows lives in LDS (at most 32 KiB)
+        if (!(hmin > 0.0) || !(nr <= 4.0) || D.n_rows + 4 > 4096) {
             p->gather_ok = 0;
             return XRT_OK;
         }
