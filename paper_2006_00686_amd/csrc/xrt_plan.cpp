@@ -311,7 +311,7 @@ xrt_status upload(const std::vector<T>& h, void** d)
 void free_plan(xrt_plan* p)
 {
     if (!p) return;
-    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT})
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -478,6 +478,19 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
     D.rays = (const double*)p->d_rays;
     p->zero_row = -1;
     p->gather_ok = 0;
+    p->d_imgT = nullptr;
+    bool any_y = false;   // a view whose u axis runs closer to y than to x
+    for (const ViewGeom& V : T.views) any_y = any_y || std::fabs(V.B[1]) > std::fabs(V.B[0]);
+    if (D.dim == 3 && D.mode != MODE_LIST && any_y) {
+        void* ws = nullptr;
+        if (hipMalloc(&ws, (size_t)D.n_units * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            free_plan(p);
+            set_error("hipMalloc of the %lld-float forward workspace failed", (long long)D.n_units);
+            return XRT_E_NOMEM;
+        }
+        p->d_imgT = (float*)ws;
+    }
     if (p->kind == XRT_CONE_FLAT && (st = cone_gather_setup(p, T.views)) != XRT_OK) {
         free_plan(p);
         return st;

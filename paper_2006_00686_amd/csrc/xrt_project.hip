@@ -122,18 +122,54 @@ struct EmitVisit {
     }
 };
 
+// imgT: the same image with y fastest ([z][x][y]), or NULL.  A wavefront reads it when
+// the detector u axis of its view runs closer to y than to x: its lanes then step
+// along y, and the transposed layout keeps their gathers in consecutive addresses.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
-                                                     float* __restrict__ sino)
+                                                     const float* __restrict__ imgT, float* __restrict__ sino)
 {
     const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (r >= P.n_rays) return;
     const int64_t b = blockIdx.y;
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
-    FwdVisit v{img + b * P.n_units, (int32_t)(P.n_units * 4), 0.0};
+    const float* base = img + b * P.n_units;
+    if constexpr (MODE != MODE_LIST) {
+        if (imgT != nullptr) {
+            const uint32_t per_view = (uint32_t)P.n_rows * (uint32_t)P.n_cols;
+            const uint32_t view0 = __builtin_amdgcn_readfirstlane((uint32_t)r / per_view);
+            const ViewGeom& V = P.views[view0];
+            if (fabs(V.B[1]) > fabs(V.B[0])) {
+                base = imgT;
+                R.st[0] = P.ny;
+                R.st[1] = 1;
+            }
+        }
+    }
+    FwdVisit v{base, (int32_t)(P.n_units * 4), 0.0};
     walk<DIM>(P, R, v);
     sino[b * P.n_rays + r] = (float)(v.acc * R.scale);
+}
+
+// out[z][x][y] = in[z][y][x]
+__global__ __launch_bounds__(kBlock) void k_transpose_xy(const float* __restrict__ in, float* __restrict__ out,
+                                                          int32_t nx, int32_t ny, int32_t ytiles)
+{
+    __shared__ float tile[32][33];
+    const int32_t z = blockIdx.y / ytiles;
+    const int32_t y0 = (blockIdx.y - z * ytiles) * 32, x0 = blockIdx.x * 32;
+    const int32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t slab = (int64_t)z * nx * ny;
+    for (int32_t yy = ty; yy < 32; yy += kBlock / 32) {
+        const int32_t y = y0 + yy, x = x0 + tx;
+        if (y < ny && x < nx) tile[yy][tx] = in[slab + (int64_t)y * nx + x];
+    }
+    __syncthreads();
+    for (int32_t xx = ty; xx < 32; xx += kBlock / 32) {
+        const int32_t x = x0 + xx, y = y0 + tx;
+        if (y < ny && x < nx) out[slab + (int64_t)x * ny + y] = tile[tx][xx];
+    }
 }
 
 template <int DIM, int MODE>
@@ -230,7 +266,20 @@ xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s)
 xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s)
 {
     const DevPlan& P = p->dp;
-    return dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, sino);
+    if (p->d_imgT == nullptr)
+        return dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, (const float*)nullptr, sino);
+    const int32_t ytiles = (P.ny + 31) / 32;
+    for (int b = 0; b < batch; ++b) {
+        const float* im = img + (int64_t)b * P.n_units;
+        hipLaunchKernelGGL(k_transpose_xy, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ytiles * P.nz)), dim3(kBlock),
+                           0, s, im, p->d_imgT, P.nx, P.ny, ytiles);
+        xrt_status st = hip_fail(hipGetLastError(), "transpose launch");
+        if (st != XRT_OK) return st;
+        st = dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), 1u), s, im, (const float*)p->d_imgT,
+                            sino + (int64_t)b * P.n_rays);
+        if (st != XRT_OK) return st;
+    }
+    return XRT_OK;
 }
 
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,

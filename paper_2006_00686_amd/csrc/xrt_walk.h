@@ -38,6 +38,7 @@ struct Ray {
     double q[3];    // index-space point
     double w[3];    // index-space direction (per unit of the ray parameter)
     double scale;   // physical length per unit of the ray parameter (|d|)
+    int32_t st[3];  // memory strides of the x, y, z unit indices in the image read
 };
 
 // Ray of linear index r (sinogram order [view][row][col]) in index space.
@@ -87,6 +88,9 @@ XRT_HD void make_ray(const DevPlan& P, int32_t r, Ray& R)
     R.w[1] = -d[1] * P.ay;
     R.w[2] = -d[2] * P.az;
     R.scale = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    R.st[0] = 1;
+    R.st[1] = P.nx;
+    R.st[2] = P.nx * P.ny;
 }
 
 // State of one axis during the walk.
@@ -124,7 +128,7 @@ XRT_HD bool setup_axes(const DevPlan& P, const Ray& R, Axis* ax,
                                            double& tin, double& tout)
 {
     const int32_t n[3] = {P.nx, P.ny, P.nz};
-    const int32_t st[3] = {1, P.nx, P.nx * P.ny};
+    const int32_t st[3] = {R.st[0], R.st[1], R.st[2]};
     tin = -kInf;
     tout = kInf;
     bool inside = true;
