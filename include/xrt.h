@@ -139,6 +139,29 @@ xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double e
 xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps,
                         const int64_t* d_offsets, int32_t* d_idx, float* d_len, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * Batched vector kernels of the iterative reconstructions built on the transform (CGLS,
+ * Landweber; the paper's motivation in the Introduction).  Vectors are float32
+ * [batch][n] contiguous; scalars are FP64, device-resident, one per batch member, so a
+ * solver iteration never synchronises with the host.
+ * --------------------------------------------------------------------------------- */
+
+/* d_out[b] = sum_i d_a[b][i] * d_b[b][i], accumulated in FP64 in a fixed order
+ * (deterministic).  d_work: device scratch of at least 64 * batch doubles. */
+xrt_status xrt_vec_dot(int64_t n, int32_t batch, const float* d_a, const float* d_b, double* d_work,
+                       double* d_out, void* stream);
+
+/* d_y[b] += sign * (d_num[b] / d_den[b]) * d_x[b]; a zero denominator adds nothing. */
+xrt_status xrt_vec_axpy_ratio(int64_t n, int32_t batch, const double* d_num, const double* d_den, double sign,
+                              const float* d_x, float* d_y, void* stream);
+
+/* d_p[b] = d_s[b] + (d_num[b] / d_den[b]) * d_p[b]; a zero denominator gives d_s[b]. */
+xrt_status xrt_vec_xpby_ratio(int64_t n, int32_t batch, const double* d_num, const double* d_den, const float* d_s,
+                              float* d_p, void* stream);
+
+/* d_y = a * d_x + b * d_y over n elements. */
+xrt_status xrt_vec_axpby(int64_t n, double a, const float* d_x, double b, float* d_y, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* xrt_status_str(int32_t status);
 

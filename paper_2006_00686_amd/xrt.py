@@ -63,8 +63,13 @@ def _lib():
         lib.xrt_status_str.argtypes = [i32]
         lib.xrt_status_str.restype = ctypes.c_char_p
         lib.xrt_last_error.restype = ctypes.c_char_p
+        lib.xrt_vec_dot.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+        lib.xrt_vec_axpy_ratio.argtypes = [i64, i32, vp, vp, ctypes.c_double, vp, vp, vp]
+        lib.xrt_vec_xpby_ratio.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+        lib.xrt_vec_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
-                  "xrt_ray_hit_counts", "xrt_ray_hits"):
+                  "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
+                  "xrt_vec_xpby_ratio", "xrt_vec_axpby"):
             getattr(lib, f).restype = ctypes.c_int32
         _LIB = lib
     return _LIB
@@ -218,3 +223,40 @@ class Plan:
         _check(_lib().xrt_ray_hits(self._h, first, n, eps, _ptr(offs), _ptr(idx), _ptr(ln), _stream(self.device)),
                "xrt_ray_hits")
         return offs, idx[:total], ln[:total]
+
+
+# ------------------------------------------------------------------ batched vector kernels
+
+
+def _vec_args(t: torch.Tensor, batch: int):
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("vectors must be contiguous float32 on the GPU")
+    return t.numel() // batch
+
+
+def vec_dot(a: torch.Tensor, b: torch.Tensor, batch: int, work: torch.Tensor, out: torch.Tensor):
+    """out[b] = <a[b], b[b]> in FP64 (out: float64 [batch]; work: float64 >= 64*batch)."""
+    n = _vec_args(a, batch)
+    _check(_lib().xrt_vec_dot(n, batch, _ptr(a), _ptr(b), _ptr(work), _ptr(out), _stream(a.device.index)),
+           "xrt_vec_dot")
+    return out
+
+
+def vec_axpy_ratio(num: torch.Tensor, den: torch.Tensor, sign: float, x: torch.Tensor, y: torch.Tensor, batch: int):
+    """y[b] += sign * num[b]/den[b] * x[b]."""
+    n = _vec_args(x, batch)
+    _check(_lib().xrt_vec_axpy_ratio(n, batch, _ptr(num), _ptr(den), float(sign), _ptr(x), _ptr(y),
+                                     _stream(x.device.index)), "xrt_vec_axpy_ratio")
+
+
+def vec_xpby_ratio(num: torch.Tensor, den: torch.Tensor, s: torch.Tensor, p: torch.Tensor, batch: int):
+    """p[b] = s[b] + num[b]/den[b] * p[b]."""
+    n = _vec_args(s, batch)
+    _check(_lib().xrt_vec_xpby_ratio(n, batch, _ptr(num), _ptr(den), _ptr(s), _ptr(p), _stream(s.device.index)),
+           "xrt_vec_xpby_ratio")
+
+
+def vec_axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor):
+    """y = a x + b y."""
+    n = _vec_args(x, 1)
+    _check(_lib().xrt_vec_axpby(n, float(a), _ptr(x), float(b), _ptr(y), _stream(x.device.index)), "xrt_vec_axpby")
