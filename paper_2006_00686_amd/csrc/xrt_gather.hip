@@ -226,6 +226,83 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
     }
 }
 
+// ---------------------------------------------------------------------------------
+// 2D gather adjoint (every 2D scan kind): one lane per pixel, BB images per lane.  Per
+// view the pixel's shadow on the detector gives the candidate bins; each candidate ray
+// is clipped against the pixel (C_low < C_up of eq. conditions_2D_1, half-open faces)
+// and adds g * len.  Deterministic: fixed view and bin order.
+template <int MODE, int BB>
+__global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __restrict__ sino,
+                                                      float* __restrict__ img, int32_t batch)
+{
+    const int32_t pix = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (pix >= P.nx * P.ny) return;
+    const int32_t b0 = blockIdx.y * BB;
+    const int32_t i = pix % P.nx, j = pix / P.nx;
+    const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
+    const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
+    const double idu = 1.0 / P.du;
+    double acc[BB];
+#pragma unroll
+    for (int q = 0; q < BB; ++q) acc[q] = 0.0;
+    for (int32_t v = 0; v < P.n_views; ++v) {
+        const ViewGeom& V = P.views[v];
+        const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
+        // detector coordinate of the four corners
+        double umin = kInf, umax = -kInf;
+#pragma unroll
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const double px = ((cnr & 1) ? xb : xa) - Ax, py = ((cnr & 2) ? yb : ya) - Ay;
+            double u;
+            if constexpr (MODE == MODE_PARALLEL) {
+                u = fma(px, Bx, py * By);                        // p = u B (+ t E)
+            } else if constexpr (MODE == MODE_DIVERGENT) {
+                const double e2 = Ex * Ex + Ey * Ey;             // |E|^2 = sdd^2
+                u = e2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+            } else {
+                u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));   // equiangular gamma
+            }
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
+        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
+        for (int32_t c = c0; c <= c1; ++c) {
+            const double u = fma((double)c, P.du, P.ubase);
+            double sx, sy, dx, dy;
+            if constexpr (MODE == MODE_PARALLEL) {
+                sx = fma(u, Bx, Ax);
+                sy = fma(u, By, Ay);
+                dx = Ex;
+                dy = Ey;
+            } else if constexpr (MODE == MODE_DIVERGENT) {
+                sx = Ax;
+                sy = Ay;
+                dx = fma(u, Bx, Ex);
+                dy = fma(u, By, Ey);
+            } else {
+                const double ca = P.col_cs[2 * c], sa = P.col_cs[2 * c + 1];
+                sx = Ax;
+                sy = Ay;
+                dx = fma(ca, Ex, sa * Bx);
+                dy = fma(ca, Ey, sa * By);
+            }
+            double tin = -kInf, tout = kInf;
+            axis_interval(xa - sx, xb - sx, dx, true, tin, tout);
+            axis_interval(ya - sy, yb - sy, dy, false, tin, tout);
+            if (!(tin < tout)) continue;
+            const double len = (tout - tin) * sqrt(dx * dx + dy * dy);   // C_up - C_low, physical
+            const int64_t r = (int64_t)v * P.n_cols + c;
+#pragma unroll
+            for (int q = 0; q < BB; ++q)
+                if (b0 + q < batch) acc[q] = fma((double)sino[(int64_t)(b0 + q) * P.n_rays + r], len, acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BB; ++q)
+        if (b0 + q < batch) img[(int64_t)(b0 + q) * P.n_units + pix] = (float)acc[q];
+}
+
 template <int KB, int NR>
 xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
 {
@@ -259,6 +336,28 @@ xrt_status launch_nr(const xrt_plan* p, const float* gT, float* img, hipStream_t
 }
 
 }  // namespace
+
+xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    constexpr int BB = 8;
+    const dim3 grid((unsigned)((P.nx * P.ny + kBlock - 1) / kBlock), (unsigned)((batch + BB - 1) / BB));
+    switch (P.mode) {
+        case MODE_PARALLEL:
+            hipLaunchKernelGGL((k_gather2d<MODE_PARALLEL, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            break;
+        case MODE_DIVERGENT:
+            hipLaunchKernelGGL((k_gather2d<MODE_DIVERGENT, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            break;
+        case MODE_ARC:
+            hipLaunchKernelGGL((k_gather2d<MODE_ARC, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            break;
+        default:
+            set_error("no gather adjoint for ray lists");
+            return XRT_E_UNSUPPORTED;
+    }
+    return hip_fail(hipGetLastError(), "2D gather launch");
+}
 
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
                                       hipStream_t s)

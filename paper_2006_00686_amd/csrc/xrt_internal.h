@@ -66,6 +66,7 @@ struct xrt_plan {
     // y-fastest copy of one image for the forward projection of views whose detector
     // u axis runs along y (3D scans, owned by the plan), or NULL
     float* d_imgT;
+    int32_t gather2d_ok;   // 2D scan whose image lies in front of every source position
 };
 
 namespace xrt {
@@ -97,4 +98,6 @@ xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s);
 // Voxel-driven gather adjoint for flat-detector cone beams (xrt_gather.hip).
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
                                       hipStream_t s);
+// Voxel-driven gather adjoint for 2D scans (xrt_gather.hip).
+xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s);
 }  // namespace xrt

@@ -479,6 +479,22 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
     p->zero_row = -1;
     p->gather_ok = 0;
     p->d_imgT = nullptr;
+    // 2D gather: the detector coordinate of a pixel's corners bounds its bins when the
+    // image lies in front of every source (divergent kinds) -- same test as the cone's
+    p->gather2d_ok = 0;
+    if (D.dim == 2 && D.mode != MODE_LIST) {
+        p->gather2d_ok = 1;
+        if (D.mode != MODE_PARALLEL) {
+            for (const ViewGeom& V : T.views) {
+                const double en = std::sqrt(V.E[0] * V.E[0] + V.E[1] * V.E[1]);
+                for (int cnr = 0; cnr < 4; ++cnr) {
+                    const double P[2] = {D.px0 + ((cnr & 1) ? D.nx * D.pdx : 0.0), D.py0 - ((cnr & 2) ? D.ny * D.pdy : 0.0)};
+                    const double depth = ((P[0] - V.A[0]) * V.E[0] + (P[1] - V.A[1]) * V.E[1]) / en;
+                    if (!(depth > 1e-6 * en)) p->gather2d_ok = 0;
+                }
+            }
+        }
+    }
     bool any_y = false;   // a view whose u axis runs closer to y than to x
     for (const ViewGeom& V : T.views) any_y = any_y || std::fabs(V.B[1]) > std::fabs(V.B[0]);
     if (D.dim == 3 && D.mode != MODE_LIST && any_y) {
@@ -533,15 +549,18 @@ xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_
         set_error("unknown adjoint mode %d", mode);
         return XRT_E_ARG;
     }
-    const bool has_gather = plan->kind == XRT_CONE_FLAT && plan->gather_ok;
-    if (mode == XRT_ADJ_GATHER && !has_gather) {
-        set_error("the voxel-driven adjoint needs a flat-detector cone scan with the image in front of "
-                  "every source position");
+    const bool cone_gather = plan->kind == XRT_CONE_FLAT && plan->gather_ok;
+    const bool gather2d = plan->gather2d_ok != 0;
+    if (mode == XRT_ADJ_GATHER && !cone_gather && !gather2d) {
+        set_error("the voxel-driven adjoint needs a 2D scan or a flat-detector cone scan with the image in "
+                  "front of every source position");
         return XRT_E_UNSUPPORTED;
     }
     DeviceGuard guard(plan->device);
-    if (mode == XRT_ADJ_GATHER || (mode == XRT_ADJ_AUTO && has_gather))
+    if (mode != XRT_ADJ_SCATTER && cone_gather)
         return launch_adjoint_cone_gather(plan, d_sino, d_img, batch, (hipStream_t)stream);
+    if (mode != XRT_ADJ_SCATTER && gather2d)
+        return launch_adjoint_gather2d(plan, d_sino, d_img, batch, (hipStream_t)stream);
     return launch_adjoint_scatter(plan, d_sino, d_img, batch, (hipStream_t)stream);
 }
 

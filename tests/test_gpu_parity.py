@@ -139,10 +139,10 @@ def test_adjoint_scatter_parity(xrt, name, grid, scan):
     H.assert_within_bar(got, ref, scl, what=f"adjoint {name}")
 
 
-CONE_SCANS = [s for s in SCANS if s[2]["kind"] == "cone_flat"]
+GATHER_SCANS = [s for s in SCANS if s[2]["kind"] in ("cone_flat", "par2d", "fan2d_flat", "fan2d_arc")]
 
 
-@pytest.mark.parametrize("name,grid,scan", CONE_SCANS, ids=[s[0] for s in CONE_SCANS])
+@pytest.mark.parametrize("name,grid,scan", GATHER_SCANS, ids=[s[0] for s in GATHER_SCANS])
 def test_adjoint_gather_parity(xrt, name, grid, scan):
     rng = np.random.default_rng(6)
     sino = rng.normal(size=inputs.sino_shape(scan)).astype(np.float32)
@@ -157,11 +157,22 @@ def test_adjoint_gather_parity(xrt, name, grid, scan):
 
 
 def test_gather_unsupported_kinds(xrt):
-    name, grid, scan = SCANS[0]
+    for grid, scan in ((dict(nx=8, ny=8, nz=0), dict(kind="raylist2d", rays=[[0.5, 0.3]])),
+                       [s[1:] for s in SCANS if s[0] == "par3d"][0]):
+        plan = xrt.Plan(grid, scan)
+        with pytest.raises(xrt.XrtError) as e:
+            plan.adjoint(torch.zeros(plan.sino_shape, device=dev()), mode="gather")
+        assert e.value.status == -6
+
+
+def test_gather2d_batched_matches_single(xrt):
+    name, grid, scan = [s for s in SCANS if s[0] == "fan2d_flat"][0]
     plan = xrt.Plan(grid, scan)
-    with pytest.raises(xrt.XrtError) as e:
-        plan.adjoint(torch.zeros(plan.sino_shape, device=dev()), mode="gather")
-    assert e.value.status == -6
+    rng = np.random.default_rng(3)
+    g = torch.from_numpy(rng.normal(size=(11,) + tuple(plan.sino_shape)).astype(np.float32)).to(dev())
+    many = plan.adjoint(g, mode="gather").cpu().numpy()
+    for b in (0, 7, 8, 10):   # first and last of the 8-image chunks
+        np.testing.assert_array_equal(many[b], plan.adjoint(g[b].contiguous(), mode="gather").cpu().numpy())
 
 
 @pytest.mark.parametrize("name,grid,scan", SCANS, ids=[s[0] for s in SCANS])

@@ -135,10 +135,16 @@ def test_pcgls_with_identity_is_cgls(mods):
     g = plan.forward(torch.from_numpy(imgs).to(DEV))
     a, _ = solvers.cgls(op, g, iters=10)
     b, _ = solvers.pcgls(op, _Identity(), g, iters=10)
-    # same sequence of kernels; the 2D adjoint is the atomic scatter, whose summation
-    # order varies from run to run, and the Krylov recursion amplifies that noise in the
-    # iterates (not in the residual it minimises): compare residual norms
-    gn = torch.linalg.vector_norm(g.double().flatten(1), dim=1)
-    ra = torch.linalg.vector_norm((plan.forward(a) - g).double().flatten(1), dim=1) / gn
-    rb = torch.linalg.vector_norm((plan.forward(b) - g).double().flatten(1), dim=1) / gn
-    assert torch.all((ra - rb).abs() <= 1e-3 * ra + 1e-6)
+    # the same sequence of deterministic kernels (the 2D adjoint is the voxel-driven gather)
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_cgls_is_reproducible(mods):
+    solvers, xrt = mods
+    grid, scan, imgs = _small_problem()
+    plan = xrt.Plan(grid, scan)
+    op = solvers.PlanOperator(plan)
+    g = plan.forward(torch.from_numpy(imgs).to(DEV))
+    a, _ = solvers.cgls(op, g, iters=25)
+    b, _ = solvers.cgls(op, g, iters=25)
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
