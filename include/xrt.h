@@ -162,6 +162,37 @@ xrt_status xrt_vec_xpby_ratio(int64_t n, int32_t batch, const double* d_num, con
 /* d_y = a * d_x + b * d_y over n elements. */
 xrt_status xrt_vec_axpby(int64_t n, double a, const float* d_x, double b, float* d_y, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * 3x3 convolutions of the learned preconditioner's CNN (stride 1, zero padding 1, no
+ * bias): BF16 operands (weights and inputs rounded to BF16), FP32 accumulation.
+ * Tensors with one channel are float32 [batch][height][width]; tensors with 32 channels
+ * are BF16 NHWC [batch][height][width][32].  A layer cin -> cout stores FP32 weights
+ * W[cout][3][3][cin] (row kh, column kw).  Supported layers: 1->32, 32->32, 32->1.
+ *   transposed = 0: out[p][co] = sum_{kh,kw,ci} W[co][kh][kw][ci] * in[p + (kh-1, kw-1)][ci]
+ *   transposed = 1: the adjoint of that layer, out[p][ci] = sum W[co][kh][kw][ci] *
+ *                   in[p - (kh-1, kw-1)][co]; (cin, cout) still name the layer, so the
+ *                   input then has cout channels and the output cin channels.
+ * The 32->32 layer runs on MFMA (v_mfma_f32_32x32x16_bf16).
+ * --------------------------------------------------------------------------------- */
+
+/* Convolution (or its adjoint) of one layer.  d_residual (float32, single-channel outputs
+ * only, or NULL) is added to the result.  out_bf16 = 0 writes a 32-channel output as
+ * float32 NHWC instead of BF16 (single-channel outputs are always float32). */
+xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t batch, int32_t height, int32_t width,
+                       const void* d_in, const float* d_weight, const float* d_residual, void* d_out,
+                       int32_t out_bf16, void* stream);
+
+/* Floats of device workspace xrt_conv3x3_wgrad needs for layer (cin, cout); -1 if the
+ * layer is not supported. */
+int64_t xrt_conv3x3_wgrad_workspace(int32_t cin, int32_t cout);
+
+/* Weight gradient of layer (cin, cout): d_dweight[co][kh][kw][ci] = sum over batch and
+ * pixels of dout[p][co] * in[p + (kh-1, kw-1)][ci] (in: cin channels, dout: cout
+ * channels, both rounded to BF16), summed in a fixed order (deterministic). */
+xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t height, int32_t width,
+                             const void* d_in, const void* d_dout, float* d_work, int64_t work_floats,
+                             float* d_dweight, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* xrt_status_str(int32_t status);
 

@@ -1,0 +1,386 @@
+// 3x3 convolutions (stride 1, zero padding 1, no bias) of the learned preconditioner's
+// small CNN, on gfx950: BF16 operands, FP32 accumulation.
+//
+// Tensors with one channel are float32 [B][H][W] (images); tensors with 32 channels are
+// BF16 NHWC [B][H][W][32].  A layer with cin -> cout channels keeps its FP32 master
+// weights as W[cout][3][3][cin]; kernels round them to BF16 when loading.
+//   conv:        out[p][co] = sum_{t, ci} W[co][t][ci] * in[p + t][ci]
+//   transposed:  out[p][ci] = sum_{t, co} W[co][t][ci] * in[p - t][co]
+// (t runs over the 3x3 offsets).  The transposed convolution is the adjoint of the
+// convolution and is computed by the same kernels reading the weights flipped and
+// transposed.  Weight gradient: dW[co][t][ci] = sum_p dout[p][co] * in[p + t][ci].
+//
+// The 32 -> 32 layer is a dense contraction (implicit GEMM: M = pixels, N = 32 output
+// channels, K = 9 x 32) on v_mfma_f32_32x32x16_bf16; its weight gradient (M = 32, N = 32
+// per offset, K = pixels) also runs on MFMA after an LDS transpose.  The 1 -> 32 and
+// 32 -> 1 layers (K = 9, or one output channel) run on the vector ALUs.
+#include <hip/hip_runtime.h>
+
+#include "xrt_internal.h"
+
+namespace xrt {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kCB = 256;
+
+__device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
+
+// weight of the convolution read by a kernel running a (cin -> cout) convolution, from
+// the stored weights of layer L: direct (L is cin -> cout) or transposed (L is
+// cout -> cin, flipped).  t = 3*kh + kw of the running convolution.
+__device__ __forceinline__ float wload(const float* W, bool tr, int co, int t, int ci, int cin, int cout)
+{
+    if (!tr) return W[(co * 9 + t) * cin + ci];
+    // layer L: cin_L = cout, cout_L = cin; W_L[c_L][t_L][i_L] with c_L = ci, i_L = co, t_L = 8 - t
+    return W[(ci * 9 + (8 - t)) * cout + co];
+}
+
+// ------------------------------------------------------------------ 1 -> 32 (VALU)
+template <bool OUT_BF16>
+__global__ __launch_bounds__(kCB) void k_conv_1to32(const float* __restrict__ x, const float* __restrict__ W, int tr,
+                                                     void* __restrict__ out, int32_t B, int32_t H, int32_t Wd)
+{
+    const int64_t p = (int64_t)blockIdx.x * kCB + threadIdx.x;
+    if (p >= (int64_t)B * H * Wd) return;
+    const int32_t w = (int32_t)(p % Wd), h = (int32_t)((p / Wd) % H);
+    const int64_t img = p - ((int64_t)h * Wd + w);
+    float xin[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int32_t hh = h + t / 3 - 1, ww = w + t % 3 - 1;
+        xin[t] = (hh >= 0 && hh < H && ww >= 0 && ww < Wd) ? bf(x[img + (int64_t)hh * Wd + ww]) : 0.0f;
+    }
+#pragma unroll
+    for (int co = 0; co < 32; co += 2) {
+        float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            a0 = fmaf(bf(wload(W, tr, co, t, 0, 1, 32)), xin[t], a0);
+            a1 = fmaf(bf(wload(W, tr, co + 1, t, 0, 1, 32)), xin[t], a1);
+        }
+        if constexpr (OUT_BF16) {
+            __bf16* o = (__bf16*)out + p * 32 + co;
+            o[0] = (__bf16)a0;
+            o[1] = (__bf16)a1;
+        } else {
+            float* o = (float*)out + p * 32 + co;
+            o[0] = a0;
+            o[1] = a1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 32 -> 1 (VALU)
+// out[p] = residual[p] + sum (residual may be NULL)
+__global__ __launch_bounds__(kCB) void k_conv_32to1(const __bf16* __restrict__ x, const float* __restrict__ W, int tr,
+                                                     const float* __restrict__ residual, float* __restrict__ out,
+                                                     int32_t B, int32_t H, int32_t Wd)
+{
+    const int64_t p = (int64_t)blockIdx.x * kCB + threadIdx.x;
+    if (p >= (int64_t)B * H * Wd) return;
+    const int32_t w = (int32_t)(p % Wd), h = (int32_t)((p / Wd) % H);
+    const int64_t img = p - ((int64_t)h * Wd + w);
+    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int32_t hh = h + t / 3 - 1, ww = w + t % 3 - 1;
+        if (hh < 0 || hh >= H || ww < 0 || ww >= Wd) continue;
+        const uint4* src = (const uint4*)(x + (img + (int64_t)hh * Wd + ww) * 32);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint4 q = src[v];
+            const uint32_t words[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t bits = (words[e >> 1] >> ((e & 1) * 16)) << 16;
+                const float a = __builtin_bit_cast(float, bits);
+                acc = fmaf(bf(wload(W, tr, 0, t, v * 8 + e, 32, 1)), a, acc);
+            }
+        }
+    }
+    out[p] = (residual ? residual[p] : 0.0f) + acc;
+}
+
+// ------------------------------------------------------------------ 32 -> 32 (MFMA)
+// One wavefront: 32 consecutive pixels of one image row x 32 output channels.
+// K = 18 steps of 16 (offset t = s / 2, input channels (s % 2) * 16 .. + 16).
+template <bool OUT_BF16>
+__global__ __launch_bounds__(kCB) void k_conv_32to32(const __bf16* __restrict__ x, const float* __restrict__ W, int tr,
+                                                      void* __restrict__ out, int32_t B, int32_t H, int32_t Wd)
+{
+    const int32_t lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * (kCB / 64) + (threadIdx.x >> 6);
+    const int32_t wt = (Wd + 31) / 32;
+    if (tile >= (int64_t)B * H * wt) return;
+    const int32_t w0 = (int32_t)(tile % wt) * 32;
+    const int64_t bh = tile / wt;
+    const int32_t h = (int32_t)(bh % H);
+    const int64_t img = (bh / H) * (int64_t)H * Wd;
+    const int32_t m = lane & 31, kb = lane >> 5;
+
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 18; ++s) {
+        const int t = s >> 1, ci0 = (s & 1) * 16 + kb * 8;
+        // B operand: W[co = lane % 32][t][ci0 .. ci0 + 7]
+        bf16x8 bw;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bw[e] = (__bf16)wload(W, tr, m, t, ci0 + e, 32, 32);
+        // A operand: in[pixel (h + kh - 1, w0 + m + kw - 1)][ci0 .. ci0 + 7]
+        const int32_t hh = h + t / 3 - 1, ww = w0 + m + t % 3 - 1;
+        bf16x8 ax;
+        if (hh >= 0 && hh < H && ww >= 0 && ww < Wd) {
+            const uint4 q = *(const uint4*)(x + (img + (int64_t)hh * Wd + ww) * 32 + ci0);
+            ax = __builtin_bit_cast(bf16x8, q);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ax[e] = (__bf16)0.0f;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bw, acc, 0, 0, 0);
+    }
+    // D[i] of lane l: pixel 8 (i / 4) + 4 (l / 32) + i % 4, channel l % 32
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int32_t px = w0 + 8 * (i >> 2) + 4 * kb + (i & 3);
+        if (px < Wd) {
+            const int64_t o = (img + (int64_t)h * Wd + px) * 32 + m;
+            if constexpr (OUT_BF16)
+                ((__bf16*)out)[o] = (__bf16)acc[i];
+            else
+                ((float*)out)[o] = acc[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weight gradients
+// Per-wave partial sums part[wave][cout][9][cin], reduced in a fixed order afterwards.
+
+// 32 -> 32 on MFMA: per 32-pixel row tile, the tile of dout (32 px x 32 co) and three
+// column-shifted copies of the input rows h-1..h+1 (32 px x 32 ci each) are staged in
+// LDS channel-major, so both operands (8 consecutive pixels of one channel) are aligned
+// 16-byte LDS reads.  D (per offset t) = dout^T (32 co x px) * in_shift (px x 32 ci).
+constexpr int kWgWaves = 2;
+
+__global__ __launch_bounds__(64 * kWgWaves) void k_wgrad_32x32(const __bf16* __restrict__ x,
+                                                               const __bf16* __restrict__ dy, float* __restrict__ part,
+                                                               int32_t B, int32_t H, int32_t Wd, int64_t ntiles)
+{
+    // per wave: dy [32 co][32 px] and x [3 kw][3 kh][32 ci][32 px]
+    __shared__ __attribute__((aligned(16))) __bf16 sdy[kWgWaves][32][32];
+    __shared__ __attribute__((aligned(16))) __bf16 sx[kWgWaves][9][32][32];
+    const int32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t m = lane & 31, kb = lane >> 5;
+    const int64_t gw = (int64_t)blockIdx.x * kWgWaves + wv, nw = (int64_t)gridDim.x * kWgWaves;
+    const int32_t wt = (Wd + 31) / 32;
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
+    for (int64_t tile = gw; tile < ntiles; tile += nw) {
+        const int32_t w0 = (int32_t)(tile % wt) * 32;
+        const int64_t bh = tile / wt;
+        const int32_t h = (int32_t)(bh % H);
+        const int64_t img = (bh / H) * (int64_t)H * Wd;
+        // stage: lane = (pixel column lane % 32, channel half lane / 32); 16 channels as
+        // two 16-byte loads, written channel-major into LDS
+        {
+            const int32_t px = lane & 31, half = lane >> 5;
+            const int32_t ww = w0 + px;
+            bf16x8 v0, v1;
+            const bool okd = ww < Wd;
+            if (okd) {
+                const uint4* src = (const uint4*)(dy + (img + (int64_t)h * Wd + ww) * 32 + half * 16);
+                v0 = __builtin_bit_cast(bf16x8, src[0]);
+                v1 = __builtin_bit_cast(bf16x8, src[1]);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                sdy[wv][half * 16 + e][px] = okd ? v0[e] : (__bf16)0.0f;
+                sdy[wv][half * 16 + 8 + e][px] = okd ? v1[e] : (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int32_t hh = h + t / 3 - 1, wx = ww + t % 3 - 1;
+                const bool ok = ww < Wd && hh >= 0 && hh < H && wx >= 0 && wx < Wd;
+                if (ok) {
+                    const uint4* src = (const uint4*)(x + (img + (int64_t)hh * Wd + wx) * 32 + half * 16);
+                    v0 = __builtin_bit_cast(bf16x8, src[0]);
+                    v1 = __builtin_bit_cast(bf16x8, src[1]);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    sx[wv][t][half * 16 + e][px] = ok ? v0[e] : (__bf16)0.0f;
+                    sx[wv][t][half * 16 + 8 + e][px] = ok ? v1[e] : (__bf16)0.0f;
+                }
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        // two K-steps of 16 pixels
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int px0 = ks * 16 + kb * 8;
+            const bf16x8 a = *(const bf16x8*)&sdy[wv][m][px0];   // A: dout^T [co = m][px]
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const bf16x8 b = *(const bf16x8*)&sx[wv][t][m][px0];   // B: in [px][ci = m]
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // D[i] of lane l: co = 8 (i / 4) + 4 (l / 32) + i % 4, ci = l % 32
+    float* dst = part + gw * (32 * 9 * 32);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int co = 8 * (i >> 2) + 4 * kb + (i & 3);
+            dst[(co * 9 + t) * 32 + m] = acc[t][i];
+        }
+}
+
+// thin layers on the vector ALUs: IN32 = (cin 32, cout 1), else (cin 1, cout 32).  A
+// block is 32 channels (of the 32-channel side) x 8 pixel lanes; each thread keeps the 9
+// offsets of its channel; the 8 lanes are summed through LDS in a fixed order.
+template <bool IN32>
+__global__ __launch_bounds__(kCB) void k_wgrad_thin(const void* __restrict__ xin, const void* __restrict__ dyin,
+                                                     float* __restrict__ part, int32_t B, int32_t H, int32_t Wd)
+{
+    __shared__ float red[kCB / 32][32 * 9];
+    const int32_t c = threadIdx.x & 31, jl = threadIdx.x >> 5;
+    const int64_t n = (int64_t)B * H * Wd;
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    for (int64_t p = (int64_t)blockIdx.x * (kCB / 32) + jl; p < n; p += (int64_t)gridDim.x * (kCB / 32)) {
+        const int32_t w = (int32_t)(p % Wd), h = (int32_t)((p / Wd) % H);
+        const int64_t img = p - ((int64_t)h * Wd + w);
+        const float d = IN32 ? bf(((const float*)dyin)[p]) : (float)((const __bf16*)dyin)[p * 32 + c];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int32_t hh = h + t / 3 - 1, ww = w + t % 3 - 1;
+            if (hh < 0 || hh >= H || ww < 0 || ww >= Wd) continue;
+            const int64_t q = img + (int64_t)hh * Wd + ww;
+            const float xv = IN32 ? (float)((const __bf16*)xin)[q * 32 + c] : bf(((const float*)xin)[q]);
+            acc[t] = fmaf(d, xv, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) red[jl][c * 9 + t] = acc[t];
+    __syncthreads();
+    for (int k = threadIdx.x; k < 32 * 9; k += kCB) {
+        float sum = 0.0f;
+        for (int q = 0; q < kCB / 32; ++q) sum += red[q][k];
+        const int32_t cc = k / 9, t = k % 9;
+        // dW[cout][t][cin]: (1 -> 32) index cc * 9 + t; (32 -> 1) index t * 32 + cc
+        part[(int64_t)blockIdx.x * 288 + (IN32 ? t * 32 + cc : cc * 9 + t)] = sum;
+    }
+}
+
+// out[k] = sum_j part[j][k]  (fixed order)
+__global__ __launch_bounds__(kCB) void k_reduce_parts(const float* __restrict__ part, int64_t nparts, int32_t nw,
+                                                       float* __restrict__ out)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kCB + threadIdx.x);
+    if (k >= nw) return;
+    double s = 0.0;
+    for (int64_t j = 0; j < nparts; ++j) s += (double)part[j * nw + k];
+    out[k] = (float)s;
+}
+
+bool shape_ok(int32_t cin, int32_t cout) { return (cin == 1 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 1); }
+
+}  // namespace
+}  // namespace xrt
+
+using namespace xrt;
+
+extern "C" {
+
+xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t batch, int32_t height, int32_t width,
+                       const void* d_in, const float* d_weight, const float* d_residual, void* d_out,
+                       int32_t out_bf16, void* stream)
+{
+    if (!shape_ok(cin, cout) || batch < 1 || height < 1 || width < 1 || !d_in || !d_weight || !d_out) {
+        set_error("xrt_conv3x3: unsupported channels (1->32, 32->32, 32->1) or bad argument");
+        return XRT_E_ARG;
+    }
+    if (d_residual && cout != 1) {
+        set_error("xrt_conv3x3: a residual is only added to single-channel outputs");
+        return XRT_E_ARG;
+    }
+    const int64_t n = (int64_t)batch * height * width;
+    hipStream_t s = (hipStream_t)stream;
+    const int tr = transposed ? 1 : 0;
+    if (cin == 1) {
+        const dim3 g((unsigned)((n + kCB - 1) / kCB));
+        if (out_bf16)
+            hipLaunchKernelGGL(k_conv_1to32<true>, g, dim3(kCB), 0, s, (const float*)d_in, d_weight, tr, d_out, batch,
+                               height, width);
+        else
+            hipLaunchKernelGGL(k_conv_1to32<false>, g, dim3(kCB), 0, s, (const float*)d_in, d_weight, tr, d_out, batch,
+                               height, width);
+    } else if (cout == 1) {
+        hipLaunchKernelGGL(k_conv_32to1, dim3((unsigned)((n + kCB - 1) / kCB)), dim3(kCB), 0, s, (const __bf16*)d_in,
+                           d_weight, tr, d_residual, (float*)d_out, batch, height, width);
+    } else {
+        const int64_t tiles = (int64_t)batch * height * ((width + 31) / 32);
+        const dim3 g((unsigned)((tiles + kCB / 64 - 1) / (kCB / 64)));
+        if (out_bf16)
+            hipLaunchKernelGGL(k_conv_32to32<true>, g, dim3(kCB), 0, s, (const __bf16*)d_in, d_weight, tr, d_out,
+                               batch, height, width);
+        else
+            hipLaunchKernelGGL(k_conv_32to32<false>, g, dim3(kCB), 0, s, (const __bf16*)d_in, d_weight, tr, d_out,
+                               batch, height, width);
+    }
+    return hip_fail(hipGetLastError(), "xrt_conv3x3 launch");
+}
+
+int64_t xrt_conv3x3_wgrad_workspace(int32_t cin, int32_t cout)
+{
+    if (!shape_ok(cin, cout)) return -1;
+    return cin == 32 && cout == 32 ? (int64_t)1024 * kWgWaves * 32 * 9 * 32 : (int64_t)1024 * 288;
+}
+
+xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t height, int32_t width,
+                             const void* d_in, const void* d_dout, float* d_work, int64_t work_floats,
+                             float* d_dweight, void* stream)
+{
+    if (!shape_ok(cin, cout) || batch < 1 || height < 1 || width < 1 || !d_in || !d_dout || !d_work || !d_dweight ||
+        work_floats < xrt_conv3x3_wgrad_workspace(cin, cout)) {
+        set_error("xrt_conv3x3_wgrad: unsupported channels, bad argument or workspace too small");
+        return XRT_E_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t nw = cout * 9 * cin;
+    int64_t nparts;
+    if (cin == 32 && cout == 32) {
+        const int64_t tiles = (int64_t)batch * height * ((width + 31) / 32);
+        int64_t blocks = (tiles + kWgWaves - 1) / kWgWaves;
+        if (blocks > 1024) blocks = 1024;
+        hipLaunchKernelGGL(k_wgrad_32x32, dim3((unsigned)blocks), dim3(64 * kWgWaves), 0, s, (const __bf16*)d_in,
+                           (const __bf16*)d_dout, d_work, batch, height, width, tiles);
+        nparts = blocks * kWgWaves;
+    } else {
+        const int64_t n = (int64_t)batch * height * width;
+        int64_t blocks = (n + kCB / 32 - 1) / (kCB / 32);
+        if (blocks > 1024) blocks = 1024;
+        if (cin == 1)
+            hipLaunchKernelGGL((k_wgrad_thin<false>), dim3((unsigned)blocks), dim3(kCB), 0, s, d_in, d_dout, d_work,
+                               batch, height, width);
+        else
+            hipLaunchKernelGGL((k_wgrad_thin<true>), dim3((unsigned)blocks), dim3(kCB), 0, s, d_in, d_dout, d_work,
+                               batch, height, width);
+        nparts = blocks;
+    }
+    xrt_status st = hip_fail(hipGetLastError(), "xrt_conv3x3_wgrad launch");
+    if (st != XRT_OK) return st;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((nw + kCB - 1) / kCB)), dim3(kCB), 0, s, (const float*)d_work,
+                       nparts, nw, d_dweight);
+    return hip_fail(hipGetLastError(), "xrt_conv3x3_wgrad reduce launch");
+}
+
+}  // extern "C"

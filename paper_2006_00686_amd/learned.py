@@ -1,0 +1,157 @@
+"""Learned preconditioner for CGLS: P = I + C3 C2 C1, a three-layer 3x3 CNN
+(1 -> 32 -> 32 -> 1 channels, BF16 weights, FP32 accumulation) on the image.
+
+CGLS is a Krylov method for a fixed linear operator, so the preconditioner is linear:
+the layers have no bias and no activation (a nonlinear network would change the
+operator from one iteration to the next).  Right preconditioning solves
+min ||A P z - g|| and returns f = P z; its adjoint is P^T = I + C1^T C2^T C3^T, computed
+by the same kernels as transposed convolutions.  Every convolution (and, for training,
+its input and weight gradients) runs in the library's kernels.
+
+Training unrolls K iterations of right-preconditioned CGLS on sinograms the projector
+itself produces and minimises the relative data residual left after K iterations.  The
+projector, its adjoint and all convolutions are the library's kernels; the CGLS scalar
+and vector algebra of the unrolled training graph goes through torch autograd.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import autograd as xag
+from . import xrt as X
+
+
+class _Conv(torch.autograd.Function):
+    """One layer (cin -> cout), or its adjoint, with input and weight gradients."""
+
+    @staticmethod
+    def forward(ctx, x, w, cin, cout, transposed):
+        ctx.save_for_backward(x, w)
+        ctx.cfg = (cin, cout, transposed)
+        return X.conv3x3(x.contiguous(), w, cin, cout, transposed)
+
+    @staticmethod
+    def backward(ctx, dout):
+        x, w = ctx.saved_tensors
+        cin, cout, tr = ctx.cfg
+        och = cin if tr else cout
+        dout = dout.contiguous().to(torch.float32 if och == 1 else torch.bfloat16)
+        dx = X.conv3x3(dout, w, cin, cout, not tr)
+        dw = X.conv3x3_wgrad(dout, x, cin, cout) if tr else X.conv3x3_wgrad(x, dout, cin, cout)
+        return dx, dw, None, None, None
+
+
+class ConvPreconditioner(torch.nn.Module):
+    SHAPES = ((1, 32), (32, 32), (32, 1))
+
+    def __init__(self, device="cuda:0", seed: int = 0, init_scale: float = 1e-3):
+        super().__init__()
+        gen = torch.Generator().manual_seed(seed)
+        ws = []
+        for cin, cout in self.SHAPES:
+            w = torch.randn((cout, 3, 3, cin), generator=gen) * init_scale / np.sqrt(9 * cin)
+            ws.append(torch.nn.Parameter(w.to(device)))
+        self.w1, self.w2, self.w3 = ws
+
+    # -------------------------------------------------------------- operators (no grad)
+
+    @torch.no_grad()
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        h = X.conv3x3(x, self.w1.data, 1, 32)
+        h = X.conv3x3(h, self.w2.data, 32, 32)
+        y = X.conv3x3(h, self.w3.data, 32, 1, residual=x)
+        if out is not None:
+            out.copy_(y)
+            return out
+        return y
+
+    @torch.no_grad()
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        h = X.conv3x3(y, self.w3.data, 32, 1, transposed=True)
+        h = X.conv3x3(h, self.w2.data, 32, 32, transposed=True)
+        x = X.conv3x3(h, self.w1.data, 1, 32, transposed=True, residual=y)
+        if out is not None:
+            out.copy_(x)
+            return out
+        return x
+
+    # -------------------------------------------------------------- differentiable
+
+    def apply_diff(self, x: torch.Tensor) -> torch.Tensor:
+        h = _Conv.apply(x, self.w1, 1, 32, False)
+        h = _Conv.apply(h, self.w2, 32, 32, False)
+        return x + _Conv.apply(h, self.w3, 32, 1, False)
+
+    def adjoint_diff(self, y: torch.Tensor) -> torch.Tensor:
+        h = _Conv.apply(y, self.w3, 32, 1, True)
+        h = _Conv.apply(h, self.w2, 32, 32, True)
+        return y + _Conv.apply(h, self.w1, 1, 32, True)
+
+    def save(self, path: str):
+        torch.save({"w1": self.w1.detach().cpu(), "w2": self.w2.detach().cpu(), "w3": self.w3.detach().cpu()}, path)
+
+    def load(self, path: str):
+        st = torch.load(path, map_location="cpu", weights_only=True)
+        with torch.no_grad():
+            self.w1.copy_(st["w1"])
+            self.w2.copy_(st["w2"])
+            self.w3.copy_(st["w3"])
+        return self
+
+
+def _bdot(a, b):
+    return (a.double() * b.double()).flatten(1).sum(1)
+
+
+def unrolled_pcgls_residual(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, K: int) -> torch.Tensor:
+    """Relative recursive residual ||r_K|| / ||g|| per problem after K iterations of
+    right-preconditioned CGLS (z0 = 0), differentiable in P's weights."""
+    shape = (-1,) + (1,) * (g.dim() - 1)
+    r = g
+    s = P.adjoint_diff(xag.backproject(r, plan))
+    p = s
+    gamma = _bdot(s, s)
+    for _ in range(K):
+        q = xag.project(P.apply_diff(p), plan)
+        alpha = (gamma / _bdot(q, q)).float()
+        r = r - alpha.view(shape) * q
+        s = P.adjoint_diff(xag.backproject(r, plan))
+        gnew = _bdot(s, s)
+        p = s + (gnew / gamma).float().view(shape) * p
+        gamma = gnew
+    return torch.sqrt(_bdot(r, r) / _bdot(g, g))
+
+
+def training_batch(cfg: dict, plan: X.Plan, batch: int, seed0: int, device) -> torch.Tensor:
+    """Noisy sinograms of fresh random phantoms (seeds seed0 .. seed0 + batch - 1)."""
+    from . import inputs
+    g = cfg["grid"]
+    imgs = np.stack([inputs.ellipse_phantom(g["nx"], g["ny"], cfg["phantom"][1], seed0 + k) for k in range(batch)])
+    clean = plan.forward(torch.from_numpy(imgs).to(device)).cpu().numpy()
+    noisy = np.stack([inputs.poisson_sinogram(clean[k], cfg.get("photons", 1e5), seed0 + 77777 + k)
+                      for k in range(batch)]).astype(np.float32)
+    return torch.from_numpy(noisy).to(device)
+
+
+def train(plan: X.Plan, cfg: dict, steps: int = 200, batch: int = 16, K: int = 10, lr: float = 2e-3,
+          seed: int = 0, device="cuda:0", log=print) -> tuple[ConvPreconditioner, list]:
+    """Adam on the mean residual left after K unrolled PCGLS iterations."""
+    P = ConvPreconditioner(device, seed=seed)
+    opt = torch.optim.Adam(P.parameters(), lr=lr)
+    history = []
+    data_seed = 1_000_000 + 1000 * seed
+    t0 = time.perf_counter()
+    for step in range(steps):
+        g = training_batch(cfg, plan, batch, data_seed + step * batch, device)
+        loss = unrolled_pcgls_residual(plan, P, g, K).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        history.append(float(loss.item()))
+        if step % 20 == 0 or step == steps - 1:
+            log(f"[train] step {step} residual after {K} PCGLS iterations {history[-1]:.4e} "
+                f"({time.perf_counter() - t0:.1f} s)")
+    return P, history

@@ -67,9 +67,13 @@ def _lib():
         lib.xrt_vec_axpy_ratio.argtypes = [i64, i32, vp, vp, ctypes.c_double, vp, vp, vp]
         lib.xrt_vec_xpby_ratio.argtypes = [i64, i32, vp, vp, vp, vp, vp]
         lib.xrt_vec_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
+        lib.xrt_conv3x3.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, vp]
+        lib.xrt_conv3x3_wgrad_workspace.argtypes = [i32, i32]
+        lib.xrt_conv3x3_wgrad_workspace.restype = i64
+        lib.xrt_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, i64, vp, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
                   "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
-                  "xrt_vec_xpby_ratio", "xrt_vec_axpby"):
+                  "xrt_vec_xpby_ratio", "xrt_vec_axpby", "xrt_conv3x3", "xrt_conv3x3_wgrad"):
             getattr(lib, f).restype = ctypes.c_int32
         _LIB = lib
     return _LIB
@@ -260,3 +264,44 @@ def vec_axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor):
     """y = a x + b y."""
     n = _vec_args(x, 1)
     _check(_lib().xrt_vec_axpby(n, float(a), _ptr(x), float(b), _ptr(y), _stream(x.device.index)), "xrt_vec_axpby")
+
+
+# ------------------------------------------------------------------ CNN convolutions
+
+
+def _conv_in_check(t: torch.Tensor, ch: int, B: int, H: int, W: int):
+    want = (B, H, W) if ch == 1 else (B, H, W, 32)
+    dt = torch.float32 if ch == 1 else torch.bfloat16
+    if tuple(t.shape) != want or t.dtype != dt or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError(f"expected contiguous {dt} {want}, got {t.dtype} {tuple(t.shape)}")
+
+
+def conv3x3(x: torch.Tensor, weight: torch.Tensor, cin: int, cout: int, transposed: bool = False,
+            residual: torch.Tensor | None = None, out_bf16: bool = True) -> torch.Tensor:
+    """One layer (cin -> cout) of 3x3 convolution, or its adjoint (transposed=True)."""
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    ich, och = (cout, cin) if transposed else (cin, cout)
+    _conv_in_check(x, ich, B, H, W)
+    if weight.dtype != torch.float32 or not weight.is_contiguous() or weight.numel() != cout * 9 * cin:
+        raise ValueError("weight must be contiguous float32 [cout][3][3][cin]")
+    if och == 1:
+        out = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+    else:
+        out = torch.empty((B, H, W, 32), dtype=torch.bfloat16 if out_bf16 else torch.float32, device=x.device)
+    res = _ptr(residual) if residual is not None else None
+    _check(_lib().xrt_conv3x3(cin, cout, int(transposed), B, H, W, _ptr(x), _ptr(weight), res, _ptr(out),
+                              int(out_bf16), _stream(x.device.index)), "xrt_conv3x3")
+    return out
+
+
+def conv3x3_wgrad(x: torch.Tensor, dout: torch.Tensor, cin: int, cout: int) -> torch.Tensor:
+    """Weight gradient [cout][3][3][cin] of layer (cin -> cout) for input x, output grad dout."""
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    _conv_in_check(x, cin, B, H, W)
+    _conv_in_check(dout, cout, B, H, W)
+    nwork = int(_lib().xrt_conv3x3_wgrad_workspace(cin, cout))
+    work = torch.empty(nwork, dtype=torch.float32, device=x.device)
+    dw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device=x.device)
+    _check(_lib().xrt_conv3x3_wgrad(cin, cout, B, H, W, _ptr(x), _ptr(dout), _ptr(work), nwork, _ptr(dw),
+                                    _stream(x.device.index)), "xrt_conv3x3_wgrad")
+    return dw
