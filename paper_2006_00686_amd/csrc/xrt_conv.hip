@@ -308,14 +308,16 @@ xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t ba
         set_error("xrt_conv3x3: unsupported channels (1->32, 32->32, 32->1) or bad argument");
         return XRT_E_ARG;
     }
-    if (d_residual && cout != 1) {
+    const int tr = transposed ? 1 : 0;
+    // channels of the convolution the kernels run: the layer's, or swapped for its adjoint
+    const int32_t rin = tr ? cout : cin, rout = tr ? cin : cout;
+    if (d_residual && rout != 1) {
         set_error("xrt_conv3x3: a residual is only added to single-channel outputs");
         return XRT_E_ARG;
     }
     const int64_t n = (int64_t)batch * height * width;
     hipStream_t s = (hipStream_t)stream;
-    const int tr = transposed ? 1 : 0;
-    if (cin == 1) {
+    if (rin == 1) {
         const dim3 g((unsigned)((n + kCB - 1) / kCB));
         if (out_bf16)
             hipLaunchKernelGGL(k_conv_1to32<true>, g, dim3(kCB), 0, s, (const float*)d_in, d_weight, tr, d_out, batch,
@@ -323,7 +325,7 @@ xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t ba
         else
             hipLaunchKernelGGL(k_conv_1to32<false>, g, dim3(kCB), 0, s, (const float*)d_in, d_weight, tr, d_out, batch,
                                height, width);
-    } else if (cout == 1) {
+    } else if (rout == 1) {
         hipLaunchKernelGGL(k_conv_32to1, dim3((unsigned)((n + kCB - 1) / kCB)), dim3(kCB), 0, s, (const __bf16*)d_in,
                            d_weight, tr, d_residual, (float*)d_out, batch, height, width);
     } else {

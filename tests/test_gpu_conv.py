@@ -98,20 +98,22 @@ def test_preconditioner_adjoint_identity_and_gradients(X):
     # the differentiable path computes the same operators
     np.testing.assert_allclose(P.apply_diff(x).detach().cpu().numpy(), Px.cpu().numpy(), rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(P.adjoint_diff(y).detach().cpu().numpy(), Pty.cpu().numpy(), rtol=1e-6, atol=1e-6)
-    # weight gradient of <P x, y> = <C3 C2 C1 x, y>: compare with a finite difference along
-    # a weight direction (the map is linear in each layer's weights)
-    for wname in ("w1", "w2", "w3"):
-        P.zero_grad()
-        (P.apply_diff(x) * y).sum().backward()
-        w = getattr(P, wname)
-        v = torch.randn_like(w)
-        an = float((w.grad.double() * v.double()).sum())
-        eps = 1e-2 * float(w.abs().max())
-        with torch.no_grad():
-            w += eps * v
-            up = float((P.apply(x).double() * y.double()).sum())
-            w -= 2 * eps * v
-            dn = float((P.apply(x).double() * y.double()).sum())
-            w += eps * v
-        fd = (up - dn) / (2 * eps)
-        assert abs(fd - an) <= 5e-2 * abs(an) + 1e-3, (wname, fd, an)
+    # weight gradients of <P x, y> through autograd against the chain rule recomputed in
+    # FP64 from the kernels' own BF16 activations (the master weights are rounded to BF16
+    # by the kernels, so a finite difference of small size would measure that rounding)
+    P.zero_grad()
+    (P.apply_diff(x) * y).sum().backward()
+    W = [oconv.bf16(w.detach().cpu().numpy()) for w in (P.w1, P.w2, P.w3)]
+    h1 = X.conv3x3(x, P.w1.data, 1, 32)
+    h2 = X.conv3x3(h1, P.w2.data, 32, 32)
+    xn, yn = x.cpu().numpy(), y.cpu().numpy()
+    h1n, h2n = h1.float().cpu().numpy(), h2.float().cpu().numpy()
+    dh2 = oconv.bf16(oconv.conv(yn, W[2], 32, 1, transposed=True))
+    dh1 = oconv.bf16(oconv.conv(dh2, W[1], 32, 32, transposed=True))
+    refs = {"w3": (h2n, yn, 32, 1), "w2": (h1n, dh2, 32, 32), "w1": (xn, dh1, 1, 32)}
+    for wname, (a, d, ci, co) in refs.items():
+        got = getattr(P, wname).grad.cpu().numpy()
+        ref = oconv.wgrad(a, d, ci, co)
+        scl = oconv.wgrad(np.abs(a), np.abs(d), ci, co)
+        # an occasional one-ulp BF16 rounding difference of a recomputed gradient activation
+        assert np.all(np.abs(got - ref) <= 8e-3 * scl + 1e-5), (wname, np.max(np.abs(got - ref) / (scl + 1e-9)))
