@@ -182,6 +182,16 @@ xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t ba
                        const void* d_in, const float* d_weight, const float* d_residual, void* d_out,
                        int32_t out_bf16, void* stream);
 
+/* The learned preconditioner in one launch: y = x + C3 C2 C1 x, or with transposed != 0
+ * its adjoint y = x + C1^T C2^T C3^T x, for float32 images x, y [batch][height][width]
+ * (C1: 1 -> 32, C2: 32 -> 32, C3: 32 -> 1 channels; weights d_w1 [32][3][3][1],
+ * d_w2 [32][3][3][32], d_w3 [1][3][3][32] float32, rounded to BF16).  The result equals
+ * the three xrt_conv3x3 calls with BF16 hidden activations and the residual x, up to
+ * FP32 summation order; the hidden activations never leave the chip.  d_y must not
+ * overlap d_x (XRT_E_ARG). */
+xrt_status xrt_precond_apply(int32_t transposed, int32_t batch, int32_t height, int32_t width, const float* d_x,
+                             const float* d_w1, const float* d_w2, const float* d_w3, float* d_y, void* stream);
+
 /* Floats of device workspace xrt_conv3x3_wgrad needs for layer (cin, cout); -1 if the
  * layer is not supported. */
 int64_t xrt_conv3x3_wgrad_workspace(int32_t cin, int32_t cout);

@@ -291,6 +291,144 @@ __global__ __launch_bounds__(kCB) void k_reduce_parts(const float* __restrict__ 
     out[k] = (float)s;
 }
 
+// ------------------------------------------------------------------ fused P and P^T
+// y = x + C3 C2 C1 x (TR: y = x + C1^T C2^T C3^T x) for single-channel float32 images,
+// with the hidden activations rounded to BF16 exactly as the layer-by-layer kernels
+// round them, but never written to HBM: a block computes a kTH x kTW output tile, h2 on
+// the tile plus a one-pixel ring (16 rows of 32 pixels: one MFMA column tile per row),
+// h1 on a two-pixel ring (in LDS) and reads x on a three-pixel ring.
+//   C1: D[co][px] = W1[co][t] * xpatch[t][px]       (K = 9 taps padded to 16)
+//   C2: D[co][px] = W2[co][(t, ci)] * h1[(t, ci)][px] (K = 288, W2 held in registers)
+//   C3: D[t][px]  = W3[t][c] * h2[c][px]              (K = 32; D of C2 is the B operand,
+//       its channel order taken as the contraction order), then y = x + sum_t D[t][px + t].
+constexpr int kTH = 14, kTW = 30;
+constexpr int kH2R = kTH + 2, kH2C = kTW + 2;       // 16 x 32
+constexpr int kH1R = kTH + 4, kH1C = kTW + 4;       // 18 x 34
+constexpr int kXR = kTH + 6, kXC = kTW + 6;         // 20 x 36
+constexpr int kH1N = kH1R * kH1C;                   // 612
+constexpr int kH1Tiles = (kH1N + 31) / 32;          // 20
+constexpr int kH1S = 40;                            // LDS stride of an h1 pixel (bf16; 80 B)
+constexpr int kPB = 256;
+static_assert(kH2C == 32 && kH2R == 4 * (kPB / 64), "one 32-pixel row per MFMA tile, four per wave");
+static_assert(9 * kH2R * kH2C * 4 <= kH1N * kH1S * 2, "tap partials fit in the h1 buffer");
+
+template <bool TR>
+__global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, const float* __restrict__ Wa,
+                                                  const float* __restrict__ Wb, const float* __restrict__ Wc,
+                                                  float* __restrict__ y, int32_t H, int32_t Wd, int32_t tiles_x,
+                                                  int32_t tiles_y, int64_t ntiles)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sx[kXR * kXC];
+    __shared__ __attribute__((aligned(16))) __bf16 sh1[kH1N * kH1S];
+    float* su = (float*)sh1;   // tap partials [9][kH2R][kH2C], after C2 has read h1
+
+    const int32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = lane & 31, kb = lane >> 5;
+    // weights as MFMA A operands (row m of lane l = l % 32, contraction index kb * 8 + e)
+    bf16x8 a1, a2[18], a3[2];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = kb * 8 + e;
+        a1[e] = (__bf16)(t < 9 ? wload(Wa, TR, m, t, 0, 1, 32) : 0.0f);
+    }
+#pragma unroll
+    for (int st = 0; st < 18; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a2[st][e] = (__bf16)wload(Wb, TR, m, st >> 1, (st & 1) * 16 + kb * 8 + e, 32, 32);
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = st * 8 + e, c = 8 * (j >> 2) + 4 * kb + (j & 3);
+            a3[st][e] = (__bf16)(m < 9 ? wload(Wc, TR, 0, m, c, 32, 1) : 0.0f);
+        }
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int32_t tx = (int32_t)(tile % tiles_x);
+        const int64_t rest = tile / tiles_x;
+        const int32_t ty = (int32_t)(rest % tiles_y);
+        const int64_t img = (rest / tiles_y) * (int64_t)H * Wd;
+        const int32_t X0 = tx * kTW, Y0 = ty * kTH;
+        // x on the three-pixel ring, zero outside the image
+        for (int k = threadIdx.x; k < kXR * kXC; k += kPB) {
+            const int32_t iy = Y0 - 3 + k / kXC, ix = X0 - 3 + k % kXC;
+            const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+            sx[k] = (__bf16)(in ? x[img + (int64_t)iy * Wd + ix] : 0.0f);
+        }
+        __syncthreads();
+        // C1 on the h1 region (pixels P = 32 T + m, row P / kH1C, column P % kH1C)
+        for (int T = wv; T < kH1Tiles; T += kPB / 64) {
+            const int32_t P = T * 32 + m, pr = P / kH1C, pc = P % kH1C;
+            const bool valid = P < kH1N;
+            bf16x8 bx;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int t = kb * 8 + e;
+                bx[e] = (valid && t < 9) ? sx[(pr + t / 3) * kXC + pc + t % 3] : (__bf16)0.0f;
+            }
+            const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bx, f32x16{}, 0, 0, 0);
+            if (valid) {
+                const int32_t iy = Y0 - 2 + pr, ix = X0 - 2 + pc;
+                const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    // channels 8 g + 4 kb .. + 3 of pixel P
+                    __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dst[q] = (__bf16)(in ? d[4 * g + q] : 0.0f);
+                }
+            }
+        }
+        __syncthreads();
+        // C2: h2 region rows R = wv + 4 j, column m
+        f32x16 h2[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t R = wv + 4 * j;
+            f32x16 acc = {};
+#pragma unroll
+            for (int st = 0; st < 18; ++st) {
+                const int t = st >> 1;
+                const bf16x8 b =
+                    *(const bf16x8*)&sh1[((R + t / 3) * kH1C + m + t % 3) * kH1S + (st & 1) * 16 + kb * 8];
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[st], b, acc, 0, 0, 0);
+            }
+            h2[j] = acc;
+        }
+        __syncthreads();
+        // C3 tap partials into LDS (h2 zero outside the image)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t R = wv + 4 * j;
+            const int32_t iy = Y0 - 1 + R, ix = X0 - 1 + m;
+            const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+            bf16x8 b0, b1;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                b0[e] = (__bf16)(in ? h2[j][e] : 0.0f);
+                b1[e] = (__bf16)(in ? h2[j][8 + e] : 0.0f);
+            }
+            f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b0, f32x16{}, 0, 0, 0);
+            u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b1, u, 0, 0, 0);
+            // D[i] of lane l: tap 8 (i / 4) + 4 kb + i % 4 (taps 0..8 are used), pixel m
+#pragma unroll
+            for (int i = 0; i < 4; ++i) su[((4 * kb + i) * kH2R + R) * kH2C + m] = u[i];
+            if (kb == 0) su[(8 * kH2R + R) * kH2C + m] = u[4];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTH * kTW; k += kPB) {
+            const int32_t r = k / kTW, c = k % kTW, iy = Y0 + r, ix = X0 + c;
+            if (iy < H && ix < Wd) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) sum += su[(t * kH2R + r + t / 3) * kH2C + c + t % 3];
+                const int64_t o = img + (int64_t)iy * Wd + ix;
+                y[o] = x[o] + sum;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 bool shape_ok(int32_t cin, int32_t cout) { return (cin == 1 && cout == 32) || (cin == 32 && cout == 32) || (cin == 32 && cout == 1); }
 
 }  // namespace
@@ -339,6 +477,32 @@ xrt_status xrt_conv3x3(int32_t cin, int32_t cout, int32_t transposed, int32_t ba
                                batch, height, width);
     }
     return hip_fail(hipGetLastError(), "xrt_conv3x3 launch");
+}
+
+xrt_status xrt_precond_apply(int32_t transposed, int32_t batch, int32_t height, int32_t width, const float* d_x,
+                             const float* d_w1, const float* d_w2, const float* d_w3, float* d_y, void* stream)
+{
+    if (batch < 1 || height < 1 || width < 1 || !d_x || !d_w1 || !d_w2 || !d_w3 || !d_y) {
+        set_error("xrt_precond_apply: bad argument");
+        return XRT_E_ARG;
+    }
+    const int64_t n = (int64_t)batch * height * width;
+    const char *xb = (const char*)d_x, *yb = (const char*)d_y;
+    if (xb < yb + n * 4 && yb < xb + n * 4) {
+        set_error("xrt_precond_apply: output overlaps the input");
+        return XRT_E_ARG;
+    }
+    const int32_t tiles_x = (width + kTW - 1) / kTW, tiles_y = (height + kTH - 1) / kTH;
+    const int64_t ntiles = (int64_t)batch * tiles_x * tiles_y;
+    const unsigned grid = (unsigned)(ntiles < 2048 ? ntiles : 2048);
+    hipStream_t s = (hipStream_t)stream;
+    if (transposed)
+        hipLaunchKernelGGL(k_precond<true>, dim3(grid), dim3(kPB), 0, s, d_x, d_w3, d_w2, d_w1, d_y, height, width,
+                           tiles_x, tiles_y, ntiles);
+    else
+        hipLaunchKernelGGL(k_precond<false>, dim3(grid), dim3(kPB), 0, s, d_x, d_w1, d_w2, d_w3, d_y, height, width,
+                           tiles_x, tiles_y, ntiles);
+    return hip_fail(hipGetLastError(), "xrt_precond_apply launch");
 }
 
 int64_t xrt_conv3x3_wgrad_workspace(int32_t cin, int32_t cout)

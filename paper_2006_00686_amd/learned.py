@@ -60,23 +60,32 @@ class ConvPreconditioner(torch.nn.Module):
 
     @torch.no_grad()
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        h = X.conv3x3(x, self.w1.data, 1, 32)
-        h = X.conv3x3(h, self.w2.data, 32, 32)
-        y = X.conv3x3(h, self.w3.data, 32, 1, residual=x)
-        if out is not None:
-            out.copy_(y)
+        """P x in one fused launch (hidden activations stay on chip)."""
+        if out is not None and out.data_ptr() == x.data_ptr():
+            out.copy_(X.precond_apply(x, self.w1.data, self.w2.data, self.w3.data))
             return out
-        return y
+        return X.precond_apply(x, self.w1.data, self.w2.data, self.w3.data, out=out)
 
     @torch.no_grad()
     def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """P^T y in one fused launch."""
+        if out is not None and out.data_ptr() == y.data_ptr():
+            out.copy_(X.precond_apply(y, self.w1.data, self.w2.data, self.w3.data, transposed=True))
+            return out
+        return X.precond_apply(y, self.w1.data, self.w2.data, self.w3.data, transposed=True, out=out)
+
+    @torch.no_grad()
+    def apply_layers(self, x: torch.Tensor) -> torch.Tensor:
+        """P x layer by layer (the activations the training path keeps)."""
+        h = X.conv3x3(x, self.w1.data, 1, 32)
+        h = X.conv3x3(h, self.w2.data, 32, 32)
+        return X.conv3x3(h, self.w3.data, 32, 1, residual=x)
+
+    @torch.no_grad()
+    def adjoint_layers(self, y: torch.Tensor) -> torch.Tensor:
         h = X.conv3x3(y, self.w3.data, 32, 1, transposed=True)
         h = X.conv3x3(h, self.w2.data, 32, 32, transposed=True)
-        x = X.conv3x3(h, self.w1.data, 1, 32, transposed=True, residual=y)
-        if out is not None:
-            out.copy_(x)
-            return out
-        return x
+        return X.conv3x3(h, self.w1.data, 1, 32, transposed=True, residual=y)
 
     # -------------------------------------------------------------- differentiable
 
@@ -137,9 +146,11 @@ def training_batch(cfg: dict, plan: X.Plan, batch: int, seed0: int, device) -> t
 
 
 def train(plan: X.Plan, cfg: dict, steps: int = 200, batch: int = 16, K: int = 10, lr: float = 2e-3,
-          seed: int = 0, device="cuda:0", log=print) -> tuple[ConvPreconditioner, list]:
+          seed: int = 0, device="cuda:0", init: str | None = None, log=print) -> tuple[ConvPreconditioner, list]:
     """Adam on the mean residual left after K unrolled PCGLS iterations."""
     P = ConvPreconditioner(device, seed=seed)
+    if init is not None:
+        P.load(init)
     opt = torch.optim.Adam(P.parameters(), lr=lr)
     history = []
     data_seed = 1_000_000 + 1000 * seed
@@ -151,7 +162,35 @@ def train(plan: X.Plan, cfg: dict, steps: int = 200, batch: int = 16, K: int = 1
         loss.backward()
         opt.step()
         history.append(float(loss.item()))
-        if step % 20 == 0 or step == steps - 1:
+        if step % 10 == 0 or step == steps - 1:
             log(f"[train] step {step} residual after {K} PCGLS iterations {history[-1]:.4e} "
                 f"({time.perf_counter() - t0:.1f} s)")
     return P, history
+
+
+EVAL_SEED0 = 5_000_000     # held-out phantoms; training draws from 1_000_000 + 1000 * seed onwards
+
+
+def default_weights() -> str:
+    import os
+    return os.path.join(os.path.dirname(__file__), "weights", "precond_fan256_60views.pt")
+
+
+def evaluate(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, tol: float = 1e-3, max_iters: int = 3000,
+             check_every: int = 1) -> dict:
+    """Wall time from data on the device to the first iterate whose recursive residual
+    satisfies ||r|| <= tol ||g|| for every problem of the batch: plain CGLS and CGLS
+    right-preconditioned by P.  Both solvers run once untimed first (kernel loading)."""
+    from . import solvers
+    op = solvers.PlanOperator(plan)
+    solvers.cgls(op, g, 2, tol, check_every)
+    solvers.pcgls(op, P, g, 2, tol, check_every, fallback=False)
+    xc, ic = solvers.cgls(op, g, max_iters, tol, check_every)
+    xp, ip = solvers.pcgls(op, P, g, max_iters, tol, check_every)
+    return dict(cgls=dict(seconds=ic.seconds, iterations=ic.iterations, converged=ic.converged,
+                          rel_residual=ic.rel_residual[-1] if ic.rel_residual else None),
+                pcgls=dict(seconds=ip.seconds, iterations=ip.iterations, converged=ip.converged,
+                           rel_residual=ip.rel_residual[-1] if ip.rel_residual else None,
+                           fallback=ip.fallback, failure=ip.failure),
+                speedup=ic.seconds / ip.seconds if ip.seconds > 0 else None,
+                images=(xc, xp))

@@ -8,6 +8,7 @@ independent problem with its own step sizes.
 """
 from __future__ import annotations
 
+import math
 import time
 from dataclasses import dataclass, field
 
@@ -54,6 +55,8 @@ class SolveInfo:
     converged: bool = False
     rel_residual: list = field(default_factory=list)   # recursive ||r|| / ||g||, per check
     seconds: float = 0.0
+    failure: str | None = None     # "nonfinite" or "stall" when the iteration was abandoned
+    fallback: bool = False         # result comes from plain CGLS after a failed PCGLS
 
 
 class _Dots:
@@ -66,14 +69,18 @@ class _Dots:
 
 
 def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
-         finish=None) -> tuple[torch.Tensor, SolveInfo]:
+         finish=None, stall_checks: int = 0, stall_ratio: float = 0.999) -> tuple[torch.Tensor, SolveInfo]:
     """CGLS (x0 = 0): minimises ||op(x) - g|| for every batch member.
 
     Stops after `iters` iterations or once every member's recursive residual satisfies
     ||r|| <= tol ||g||.  `finish(z)` maps the iterate to the image (the preconditioner for
-    right-preconditioned CGLS)."""
+    right-preconditioned CGLS).  With a tolerance, the iteration is abandoned (info.failure)
+    when the worst residual is not finite, or, if stall_checks > 0, when it has not dropped
+    below stall_ratio times its value stall_checks checks earlier."""
     batch = g.shape[0]
     dev = g.device
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
     dots = _Dots(batch, dev)
     f64 = dict(dtype=torch.float64, device=dev)
     x = torch.zeros((batch,) + tuple(op.domain_shape), dtype=torch.float32, device=dev)
@@ -85,7 +92,6 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
     dots(s, s, gamma)
     dots(g, g, gg)
     info = SolveInfo()
-    t0 = time.perf_counter()
     for it in range(1, iters + 1):
         op.apply(p, out=q)
         dots(q, q, delta)
@@ -104,15 +110,35 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
             if worst <= tol:
                 info.converged = True
                 break
+            if not math.isfinite(worst):
+                info.failure = "nonfinite"
+                break
+            h = info.rel_residual
+            if stall_checks and len(h) > stall_checks and h[-1] > stall_ratio * h[-1 - stall_checks]:
+                info.failure = "stall"
+                break
     out = finish(x) if finish is not None else x
     torch.cuda.synchronize(dev)
     info.seconds = time.perf_counter() - t0
     return out, info
 
 
-def pcgls(op: PlanOperator, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5):
-    """Right-preconditioned CGLS: min ||A P z - g||, image f = P z."""
-    return cgls(RightPreconditioned(op, P), g, iters, tol, check_every, finish=P.apply)
+def pcgls(op: PlanOperator, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
+          fallback: bool = True, stall_checks: int = 4):
+    """Right-preconditioned CGLS: min ||A P z - g||, image f = P z.
+
+    With a tolerance and fallback=True, a preconditioned run whose worst residual becomes
+    non-finite or stalls is discarded and plain CGLS solves the problem from x0 = 0
+    (info.fallback and info.failure are set; info.seconds covers both runs)."""
+    x, info = cgls(RightPreconditioned(op, P), g, iters, tol, check_every, finish=P.apply,
+                   stall_checks=stall_checks if tol is not None else 0)
+    if info.failure is None or not fallback:
+        return x, info
+    x, plain = cgls(op, g, iters, tol, check_every)
+    plain.fallback = True
+    plain.failure = info.failure
+    plain.seconds += info.seconds
+    return x, plain
 
 
 def operator_norm_sq(op, shape, device, iters: int = 20, seed: int = 0) -> float:

@@ -71,6 +71,7 @@ def _lib():
         lib.xrt_conv3x3_wgrad_workspace.argtypes = [i32, i32]
         lib.xrt_conv3x3_wgrad_workspace.restype = i64
         lib.xrt_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, i64, vp, vp]
+        lib.xrt_precond_apply.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
                   "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
                   "xrt_vec_xpby_ratio", "xrt_vec_axpby", "xrt_conv3x3", "xrt_conv3x3_wgrad"):
@@ -305,3 +306,20 @@ def conv3x3_wgrad(x: torch.Tensor, dout: torch.Tensor, cin: int, cout: int) -> t
     _check(_lib().xrt_conv3x3_wgrad(cin, cout, B, H, W, _ptr(x), _ptr(dout), _ptr(work), nwork, _ptr(dw),
                                     _stream(x.device.index)), "xrt_conv3x3_wgrad")
     return dw
+
+
+def precond_apply(x: torch.Tensor, w1: torch.Tensor, w2: torch.Tensor, w3: torch.Tensor, transposed: bool = False,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = x + C3 C2 C1 x (transposed: x + C1^T C2^T C3^T x) in one launch; x float32 [B][H][W]."""
+    B, H, W = x.shape[0], x.shape[1], x.shape[2]
+    _conv_in_check(x, 1, B, H, W)
+    for w, n in ((w1, 32 * 9), (w2, 32 * 9 * 32), (w3, 9 * 32)):
+        if w.dtype != torch.float32 or not w.is_contiguous() or w.numel() != n or w.device != x.device:
+            raise ValueError("weights must be contiguous float32 [32][3][3][1], [32][3][3][32], [1][3][3][32]")
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _conv_in_check(out, 1, B, H, W)
+    _check(_lib().xrt_precond_apply(int(transposed), B, H, W, _ptr(x), _ptr(w1), _ptr(w2), _ptr(w3), _ptr(out),
+                                    _stream(x.device.index)), "xrt_precond_apply")
+    return out

@@ -117,3 +117,81 @@ def test_preconditioner_adjoint_identity_and_gradients(X):
         scl = oconv.wgrad(np.abs(a), np.abs(d), ci, co)
         # an occasional one-ulp BF16 rounding difference of a recomputed gradient activation
         assert np.all(np.abs(got - ref) <= 8e-3 * scl + 1e-5), (wname, np.max(np.abs(got - ref) / (scl + 1e-9)))
+
+
+def _exact_operands(rng, B, H, W):
+    """Integer-valued operands for which every hidden activation and every sum is exact in
+    BF16 / FP32 (|h1| <= 9, |h2| <= 27 * 9 = 243, |y| < 2^24) for P and for P^T: kernels
+    and reference must agree bit for bit, whatever the summation order."""
+    x = rng.integers(-1, 2, size=(B, H, W)).astype(np.float32)
+    w1 = rng.integers(-1, 2, size=(32, 3, 3, 1)).astype(np.float32)
+    co, t, ci = np.meshgrid(np.arange(32), np.arange(9), np.arange(32), indexing="ij")
+    mask = (co + ci + 5 * t) % 11 == 0          # <= 27 nonzeros per output and per input channel
+    assert mask.sum(axis=(1, 2)).max() <= 27 and mask.sum(axis=(0, 1)).max() <= 27
+    w2 = (mask * rng.choice([-1.0, 1.0], size=mask.shape)).reshape(32, 3, 3, 32).astype(np.float32)
+    w3 = rng.integers(-1, 2, size=(1, 3, 3, 32)).astype(np.float32)
+    return x, w1, w2, w3
+
+
+def _ref_chain(x, w1, w2, w3, transposed):
+    if not transposed:
+        h = oconv.bf16(oconv.conv(x, w1, 1, 32))
+        h = oconv.bf16(oconv.conv(h, w2, 32, 32))
+        return x + oconv.conv(h, w3, 32, 1)
+    h = oconv.bf16(oconv.conv(x, w3, 32, 1, transposed=True))
+    h = oconv.bf16(oconv.conv(h, w2, 32, 32, transposed=True))
+    return x + oconv.conv(h, w1, 1, 32, transposed=True)
+
+
+@pytest.mark.parametrize("transposed", [False, True])
+@pytest.mark.parametrize("B,H,W", [(2, 37, 61), (1, 14, 30), (3, 1, 1), (1, 5, 95), (2, 64, 64)])
+def test_fused_preconditioner_exact(X, transposed, B, H, W):
+    rng = np.random.default_rng(B * 1000 + H * 10 + W + transposed)
+    x, w1, w2, w3 = _exact_operands(rng, B, H, W)
+    dev = [torch.from_numpy(a).to(DEV) for a in (x, w1, w2, w3)]
+    got = X.precond_apply(*dev, transposed=transposed).cpu().numpy()
+    ref = _ref_chain(x, w1, w2, w3, transposed)
+    assert np.max(np.abs(ref)) > 10 or H * W < 16
+    np.testing.assert_array_equal(got, ref.astype(np.float32))
+    # the layer-by-layer kernels compute the same values
+    from paper_2006_00686_amd.learned import ConvPreconditioner
+    P = ConvPreconditioner(DEV)
+    with torch.no_grad():
+        P.w1.copy_(dev[1]), P.w2.copy_(dev[2]), P.w3.copy_(dev[3])
+    lay = (P.adjoint_layers(dev[0]) if transposed else P.apply_layers(dev[0])).cpu().numpy()
+    np.testing.assert_array_equal(lay, got)
+
+
+@pytest.mark.parametrize("transposed", [False, True])
+def test_fused_preconditioner_random(X, transposed):
+    """Real-valued operands: FP32 sums in a different order may round a hidden activation
+    to the neighbouring BF16 value (at most one BF16 spacing, 2^-7 relative)."""
+    rng = np.random.default_rng(17 + transposed)
+    B, H, W = 2, 45, 77
+    x = rng.normal(size=(B, H, W)).astype(np.float32)
+    w1, w2, w3 = (rng.normal(size=s).astype(np.float32) * 0.3 for s in ((32, 3, 3, 1), (32, 3, 3, 32), (1, 3, 3, 32)))
+    dev = [torch.from_numpy(a).to(DEV) for a in (x, w1, w2, w3)]
+    got = X.precond_apply(*dev, transposed=transposed).cpu().numpy()
+    ref = _ref_chain(x, w1, w2, w3, transposed)
+    a1, a2, a3 = (np.abs(oconv.bf16(w)) for w in (w1, w2, w3))
+    ax = np.abs(oconv.bf16(x))
+    if not transposed:
+        h1 = oconv.conv(ax, a1, 1, 32)
+        h2 = oconv.conv(h1, a2, 32, 32)
+        s0, s1 = oconv.conv(h2, a3, 32, 1), oconv.conv(oconv.conv(h1, a2, 32, 32), a3, 32, 1)
+    else:
+        h1 = oconv.conv(ax, a3, 32, 1, transposed=True)
+        h2 = oconv.conv(h1, a2, 32, 32, transposed=True)
+        s0 = s1 = oconv.conv(h2, a1, 1, 32, transposed=True)
+    bar = 2.0 ** -7 * (s0 + s1) + 1e-5 * s0 + 1e-6
+    assert np.all(np.abs(got - ref) <= bar), np.max(np.abs(got - ref) / bar)
+    # most outputs see no rounding flip at all and agree to FP32 summation accuracy
+    tight = np.abs(got - ref) <= 1e-5 * s0 + 1e-6
+    assert tight.mean() >= 0.5, tight.mean()
+
+
+def test_fused_preconditioner_rejects_aliasing(X):
+    x = torch.zeros((1, 8, 8), dtype=torch.float32, device=DEV)
+    w = [torch.zeros(n, dtype=torch.float32, device=DEV) for n in (288, 9216, 288)]
+    with pytest.raises(X.XrtError):
+        X.precond_apply(x, *w, out=x)
