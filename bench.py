@@ -5,8 +5,9 @@ SOD 1000, SDD 1500, flat 512 x 384 detector at spacing 1.0) on one MI355X.
 
 A step is one forward projection and one adjoint of the whole scan, with the volume
 already resident in HBM.  Prints ONE JSON line on stdout (everything else on stderr):
-metric (Mrays/s of forward + adjoint), the dominant kernel's roofline figures and the
-FP64 oracle timed on a bounded sample on the host cores.
+metric (Mrays/s of forward + adjoint), the dominant kernel's roofline figures, the
+FP64 oracle timed on a bounded sample on the host cores, and the time to a relative
+residual of 1e-3 of CGLS with and without the learned preconditioner.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -72,6 +73,30 @@ def cpu_baseline(cfg, img, views_every: int):
                       f"{m} rays), forward {t1 - t0:.2f} s + adjoint {t2 - t1:.2f} s, FP64"}
 
 
+def learned_solve(torch, dev, tol: float = 1e-3):
+    """Sparse-view fan-beam workload (64 held-out phantoms, 256^2, 60 views, Poisson noise):
+    wall time to relative residual `tol` of plain CGLS and of CGLS right-preconditioned by
+    the trained CNN, plus the true data residual of both final images."""
+    from paper_2006_00686_amd import inputs, learned, xrt
+    cfg = inputs.config(5)
+    plan = xrt.Plan(cfg["grid"], cfg["scan"], 0)
+    g = learned.training_batch(cfg, plan, cfg["batch"], learned.EVAL_SEED0, dev)
+    P = learned.ConvPreconditioner(dev).load(learned.default_weights())
+    r = learned.evaluate(plan, P, g, tol=tol)
+    xc, xp = r.pop("images")
+
+    def true_residual(x):
+        d = (plan.forward(x) - g).double().flatten(1)
+        return float(torch.sqrt((d * d).sum(1) / (g.double().flatten(1) ** 2).sum(1)).max())
+
+    return {"workload": cfg["name"], "batch": cfg["batch"], "tol": tol,
+            "cgls_s": round(r["cgls"]["seconds"], 5), "cgls_iterations": r["cgls"]["iterations"],
+            "pcgls_s": round(r["pcgls"]["seconds"], 5), "pcgls_iterations": r["pcgls"]["iterations"],
+            "speedup": round(r["speedup"], 3), "fallback": r["pcgls"]["fallback"],
+            "true_residual": {"cgls": true_residual(xc), "pcgls": true_residual(xp)},
+            "weights": os.path.relpath(learned.default_weights(), ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +104,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--adjoint", default="auto", choices=["auto", "scatter", "gather"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve comparison")
     ap.add_argument("--cpu-views-every", type=int, default=15)
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -150,6 +176,12 @@ def main():
                 "fwd_ms": round(t_fwd, 4), "adj_ms": round(t_adj, 4),
                 "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    learned = None
+    if not args.no_learned:
+        log("[bench] learned preconditioner vs plain CGLS (sparse-view fan beam, batch 64)")
+        learned = learned_solve(torch, dev)
+        log(f"[bench] learned {learned}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample")
@@ -176,6 +208,7 @@ def main():
                    "crossing_parameter_dtype": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 

@@ -115,23 +115,26 @@ def _bdot(a, b):
     return (a.double() * b.double()).flatten(1).sum(1)
 
 
-def unrolled_pcgls_residual(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, K: int) -> torch.Tensor:
-    """Relative recursive residual ||r_K|| / ||g|| per problem after K iterations of
-    right-preconditioned CGLS (z0 = 0), differentiable in P's weights."""
+def unrolled_pcgls_residuals(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, K: int) -> torch.Tensor:
+    """Relative recursive residuals ||r_k|| / ||g||, k = 1..K, of right-preconditioned
+    CGLS (z0 = 0) per problem ([K][batch]), differentiable in P's weights."""
     shape = (-1,) + (1,) * (g.dim() - 1)
+    gg = _bdot(g, g)
     r = g
     s = P.adjoint_diff(xag.backproject(r, plan))
     p = s
     gamma = _bdot(s, s)
+    out = []
     for _ in range(K):
         q = xag.project(P.apply_diff(p), plan)
         alpha = (gamma / _bdot(q, q)).float()
         r = r - alpha.view(shape) * q
+        out.append(torch.sqrt(_bdot(r, r) / gg))
         s = P.adjoint_diff(xag.backproject(r, plan))
         gnew = _bdot(s, s)
         p = s + (gnew / gamma).float().view(shape) * p
         gamma = gnew
-    return torch.sqrt(_bdot(r, r) / _bdot(g, g))
+    return torch.stack(out)
 
 
 def training_batch(cfg: dict, plan: X.Plan, batch: int, seed0: int, device) -> torch.Tensor:
@@ -145,26 +148,56 @@ def training_batch(cfg: dict, plan: X.Plan, batch: int, seed0: int, device) -> t
     return torch.from_numpy(noisy).to(device)
 
 
-def train(plan: X.Plan, cfg: dict, steps: int = 200, batch: int = 16, K: int = 10, lr: float = 2e-3,
-          seed: int = 0, device="cuda:0", init: str | None = None, log=print) -> tuple[ConvPreconditioner, list]:
-    """Adam on the mean residual left after K unrolled PCGLS iterations."""
+VAL_SEED0 = 3_000_000      # validation phantoms for model selection
+
+
+def iterations_to(plan: X.Plan, P, g: torch.Tensor, tol: float, max_iters: int = 400) -> int:
+    """PCGLS iterations until every problem's recursive residual is <= tol (max_iters + 1
+    when it does not get there)."""
+    from . import solvers
+    _, info = solvers.pcgls(solvers.PlanOperator(plan), P, g, max_iters, tol, check_every=1, fallback=False)
+    return info.iterations if info.converged else max_iters + 1
+
+
+def train(plan: X.Plan, cfg: dict, steps: int = 300, batch: int = 16, K: int = 10, lr: float = 2e-3,
+          seed: int = 0, device="cuda:0", init: str | None = None, clip: float | None = None,
+          loss_kind: str = "final", cosine: bool = False, val_every: int = 25, val_batch: int = 16,
+          tol: float = 1e-3, log=print) -> tuple[ConvPreconditioner, list]:
+    """Adam on the mean relative residual after K unrolled PCGLS iterations (loss_kind
+    "final") or on the mean log residual along all K ("trajectory"), optionally with
+    gradient-norm clipping and cosine learning-rate decay.  Every val_every steps the
+    weights are scored by the PCGLS iterations to `tol` on a fixed validation batch and
+    the best weights seen are returned (the starting weights are scored first)."""
     P = ConvPreconditioner(device, seed=seed)
     if init is not None:
         P.load(init)
     opt = torch.optim.Adam(P.parameters(), lr=lr)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, T_max=max(steps, 1)) if cosine else None
+    gval = training_batch(cfg, plan, val_batch, VAL_SEED0, device)
+    best = (iterations_to(plan, P, gval, tol), {k: v.detach().clone() for k, v in P.state_dict().items()})
+    log(f"[train] validation: {best[0]} iterations to {tol:g} at the start")
     history = []
     data_seed = 1_000_000 + 1000 * seed
     t0 = time.perf_counter()
     for step in range(steps):
         g = training_batch(cfg, plan, batch, data_seed + step * batch, device)
-        loss = unrolled_pcgls_residual(plan, P, g, K).mean()
+        res = unrolled_pcgls_residuals(plan, P, g, K)
+        loss = torch.log(res).mean() if loss_kind == "trajectory" else res[-1].mean()
         opt.zero_grad()
         loss.backward()
+        if clip is not None:
+            torch.nn.utils.clip_grad_norm_(P.parameters(), clip)
         opt.step()
-        history.append(float(loss.item()))
-        if step % 10 == 0 or step == steps - 1:
-            log(f"[train] step {step} residual after {K} PCGLS iterations {history[-1]:.4e} "
-                f"({time.perf_counter() - t0:.1f} s)")
+        if sched is not None:
+            sched.step()
+        history.append(float(res[-1].mean().item()))
+        if (step + 1) % val_every == 0 or step == steps - 1:
+            it = iterations_to(plan, P, gval, tol)
+            if it < best[0]:
+                best = (it, {k: v.detach().clone() for k, v in P.state_dict().items()})
+            log(f"[train] step {step + 1} residual after {K} PCGLS iterations {history[-1]:.4e}, "
+                f"validation {it} iterations (best {best[0]}) ({time.perf_counter() - t0:.1f} s)")
+    P.load_state_dict(best[1])
     return P, history
 
 

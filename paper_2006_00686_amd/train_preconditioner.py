@@ -20,10 +20,14 @@ from . import xrt as X
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--unroll", type=int, default=10, help="PCGLS iterations unrolled in the loss")
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--clip", type=float, default=None)
+    ap.add_argument("--loss", choices=["final", "trajectory"], default="final")
+    ap.add_argument("--cosine", action="store_true")
+    ap.add_argument("--val-every", type=int, default=25)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=learned.default_weights())
     ap.add_argument("--resume", default=None, help="weights to start from")
@@ -36,7 +40,9 @@ def main(argv=None) -> int:
     plan = X.Plan(cfg["grid"], cfg["scan"], device=0)
     t0 = time.perf_counter()
     P, hist = learned.train(plan, cfg, steps=args.steps, batch=args.batch, K=args.unroll, lr=args.lr,
-                            seed=args.seed, device=dev, init=args.resume,
+                            seed=args.seed, device=dev, init=args.resume, clip=args.clip,
+                            loss_kind=args.loss, cosine=args.cosine,
+                            val_every=args.val_every, tol=args.tol,
                             log=lambda m: print(m, flush=True))
     train_s = time.perf_counter() - t0
     import os
