@@ -203,6 +203,39 @@ xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t h
                              const void* d_in, const void* d_dout, float* d_work, int64_t work_floats,
                              float* d_dweight, void* stream);
 
+/* ---- launch shape of the forward projection (tuning; results do not depend on it) ----
+ * packet_cols = 0: a wavefront takes 64 consecutive rays in (view, row, column) order;
+ * 64, 32 or 16: a wavefront takes a packet of packet_cols detector columns x
+ * (64 / packet_cols) rows of one view (ignored for ray lists).  xcd_remap = 1 gives
+ * each of the 8 XCDs a contiguous range of packets (shared L2 working set). */
+typedef struct {
+    int32_t packet_cols;
+    int32_t xcd_remap;
+} xrt_tuning;
+
+xrt_status xrt_plan_set_tuning(xrt_plan* plan, const xrt_tuning* tuning);   /* XRT_E_ARG: bad value */
+xrt_status xrt_plan_get_tuning(const xrt_plan* plan, xrt_tuning* tuning);
+
+/* ---- batches: several plans projected by one persistent launch ----
+ * 1..32 plans of one device that share the dimension and the ray mode (no ray lists;
+ * XRT_E_UNSUPPORTED otherwise).  The caller keeps the plans alive while the batch
+ * exists; their launch shapes are taken at creation.  The forward of all members is one
+ * persistent kernel whose workgroups draw chunks of rays from a queue ordered by ray
+ * length (longest first), after one small reset kernel (and the y-fastest copies of
+ * the images of 3D plans that use them); no allocation, copy or host synchronisation
+ * happens in xrt_batch_forward / xrt_batch_adjoint, so both can be captured in a graph.
+ * The rays of one member match xrt_forward of its plan bit for bit.  Host arrays of n
+ * device pointers: images [nz][ny][nx] and sinograms of each member. */
+typedef struct xrt_batch xrt_batch;
+
+xrt_status xrt_batch_create(xrt_plan* const* plans, int32_t n, xrt_batch** out);
+xrt_status xrt_batch_destroy(xrt_batch* batch);
+xrt_status xrt_batch_forward(xrt_batch* batch, const float* const* d_imgs, float* const* d_sinos, void* stream);
+/* Adjoint of every member (xrt_adjoint of its plan with the given mode, members in
+ * queue order, each overwriting its image). */
+xrt_status xrt_batch_adjoint(xrt_batch* batch, const float* const* d_sinos, float* const* d_imgs, int32_t mode,
+                             void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* xrt_status_str(int32_t status);
 

@@ -25,6 +25,8 @@ struct ViewGeom {         // FP64 per-view vectors, see RayMode
 };
 
 // Everything a projection kernel needs, passed by value as a kernel argument.
+constexpr int kMaxBatch = 32;   // members of one xrt_batch
+
 struct DevPlan {
     int32_t dim;          // 2 or 3
     int32_t mode;         // RayMode
@@ -44,6 +46,12 @@ struct DevPlan {
     const double* col_cs;             // MODE_ARC: [n_cols][2] (cos, sin) of the column angle
     const double* row_cs;             // MODE_ARC: [n_rows][2]
     const double* rays;               // MODE_LIST: [n_rays][6] (p, d)
+    // forward launch shape (tuning; no effect on results): packet_cols = 0 enumerates
+    // rays linearly, 64 / 32 / 16 gives each wavefront a packet of packet_cols detector
+    // columns x (64 / packet_cols) rows of one view; xcd_remap = 1 hands each XCD a
+    // contiguous range of packets (workgroups are dealt to the 8 XCDs round robin)
+    int32_t packet_cols = 0;
+    int32_t xcd_remap = 0;
 };
 
 }  // namespace xrt
@@ -69,6 +77,19 @@ struct xrt_plan {
     int32_t gather2d_ok;   // 2D scan whose image lies in front of every source position
 };
 
+// Several plans (same dimension and ray mode) projected together; the plans stay owned
+// by the caller and must outlive the batch.  Their launch shapes are taken at creation.
+struct xrt_batch {
+    int device;
+    int32_t n;
+    xrt_plan* plans[xrt::kMaxBatch];
+    xrt::DevPlan hp[xrt::kMaxBatch];        // snapshots of the plans' device descriptors
+    int32_t order[xrt::kMaxBatch];          // queue order: longest rays first
+    xrt::DevPlan* d_plans;                  // device copies of hp
+    unsigned long long* d_counter;          // work-queue counter (reset by a kernel per launch)
+    uint32_t grid;                          // persistent workgroups
+};
+
 namespace xrt {
 // Host-side result of validating and expanding a grid + scan (device pointers unset).
 struct HostTables {
@@ -81,6 +102,22 @@ struct HostTables {
 // Validate and expand in FP64 on the host (no HIP calls).
 xrt_status build_tables(const xrt_grid* grid, const xrt_scan* scan, HostTables& out);
 
+// Makes a device current for the lifetime of the guard, restoring the previous one.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
 // Set by failing entry points; read by xrt_last_error().
 void set_error(const char* fmt, ...);
 xrt_status hip_fail(hipError_t e, const char* what);
@@ -88,6 +125,13 @@ xrt_status hip_fail(hipError_t e, const char* what);
 // Launchers (xrt_project.hip).
 xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch,
                           hipStream_t s);
+// One persistent launch over the members of a batch (host plan snapshots hp, device
+// copies d_plans, queue order, per-member images and sinograms).
+xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const DevPlan* d_plans, int32_t n,
+                                const int32_t* order, const float* const* imgs, float* const* sinos,
+                                unsigned long long* counter, uint32_t grid, hipStream_t s);
+xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, hipStream_t s);
+uint32_t forward_batch_blocks_per_cu();
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
                                   hipStream_t s);
 xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps,

@@ -18,21 +18,6 @@ thread_local char g_err[512] = "";
 
 constexpr double kSnap = 1e-12;
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 bool finite(double x) { return std::isfinite(x); }
 
 // Unit vector with components of magnitude <= kSnap set to exactly 0, so that a view

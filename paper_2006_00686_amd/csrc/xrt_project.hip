@@ -122,19 +122,50 @@ struct EmitVisit {
     }
 };
 
-// imgT: the same image with y fastest ([z][x][y]), or NULL.  A wavefront reads it when
-// the detector u axis of its view runs closer to y than to x: its lanes then step
-// along y, and the transposed layout keeps their gathers in consecutive addresses.
-template <int DIM, int MODE>
-__global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
-                                                     const float* __restrict__ imgT, float* __restrict__ sino)
+// Ray of thread t when a wavefront covers a packet of P.packet_cols detector columns x
+// (64 / packet_cols) rows of one view, or -1 past the detector's edge.
+__device__ __forceinline__ int32_t packet_ray(const DevPlan& P, uint64_t t)
 {
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= P.n_rays) return;
-    const int64_t b = blockIdx.y;
+    const uint32_t tw = (uint32_t)P.packet_cols, th = 64u / tw;
+    const uint32_t ct = ((uint32_t)P.n_cols + tw - 1) / tw, rt = ((uint32_t)P.n_rows + th - 1) / th;
+    const uint64_t packet = t >> 6, per_view = (uint64_t)ct * rt;
+    const uint32_t lane = (uint32_t)t & 63u;
+    const uint64_t view = packet / per_view;
+    if (view >= (uint64_t)P.n_views) return -1;
+    const uint32_t rem = (uint32_t)(packet - view * per_view);
+    const uint32_t rti = rem / ct, cti = rem - rti * ct;
+    const uint32_t row = rti * th + lane / tw, col = cti * tw + lane % tw;
+    if (row >= (uint32_t)P.n_rows || col >= (uint32_t)P.n_cols) return -1;
+    return (int32_t)(((uint32_t)view * (uint32_t)P.n_rows + row) * (uint32_t)P.n_cols + col);
+}
+
+// Ray of thread t of a forward launch (-1: no ray).
+template <int MODE>
+__device__ __forceinline__ int32_t forward_ray_of(const DevPlan& P, uint64_t t)
+{
+    if (MODE != MODE_LIST && P.packet_cols > 0) return packet_ray(P, t);
+    return t < (uint64_t)P.n_rays ? (int32_t)t : -1;
+}
+
+// Threads a forward launch enumerates.
+__host__ __device__ inline uint64_t forward_threads(const DevPlan& P)
+{
+    if (P.mode == MODE_LIST || P.packet_cols == 0) return (uint64_t)P.n_rays;
+    const uint64_t tw = (uint64_t)P.packet_cols, th = 64u / tw;
+    return (uint64_t)P.n_views * ((P.n_cols + tw - 1) / tw) * ((P.n_rows + th - 1) / th) * 64u;
+}
+
+// One ray of the forward projection.  imgT: the same image with y fastest ([z][x][y]),
+// or NULL; a wavefront reads it when the detector u axis of its view runs closer to y
+// than to x: its lanes then step along y, and the transposed layout keeps their gathers
+// in consecutive addresses.
+template <int DIM, int MODE>
+__device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const float* img, const float* imgT,
+                                            float* sino)
+{
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
-    const float* base = img + b * P.n_units;
+    const float* base = img;
     if constexpr (MODE != MODE_LIST) {
         if (imgT != nullptr) {
             const uint32_t per_view = (uint32_t)P.n_rows * (uint32_t)P.n_cols;
@@ -149,7 +180,76 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __re
     }
     FwdVisit v{base, (int32_t)(P.n_units * 4), 0.0};
     walk<DIM>(P, R, v);
-    sino[b * P.n_rays + r] = (float)(v.acc * R.scale);
+    sino[r] = (float)(v.acc * R.scale);
+}
+
+// nblocks: workgroups that carry rays; with xcd_remap the grid is rounded up to a
+// multiple of 8 and workgroup b takes logical block (b % 8) * (grid / 8) + b / 8.
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
+                                                     const float* __restrict__ imgT, float* __restrict__ sino,
+                                                     uint32_t nblocks)
+{
+    uint32_t blk = blockIdx.x;
+    if (P.xcd_remap) {
+        blk = (blk & 7u) * (gridDim.x >> 3) + (blk >> 3);
+        if (blk >= nblocks) return;
+    }
+    const int32_t r = forward_ray_of<MODE>(P, (uint64_t)blk * kBlock + threadIdx.x);
+    if (r < 0) return;
+    const int64_t b = blockIdx.y;
+    forward_one<DIM, MODE>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays);
+}
+
+// ------------------------------------------------------------------ batched (several plans)
+// One persistent launch projects every member of a batch.  The work queue lists chunks
+// of kChunkBlocks x 256 threads member by member, members in the order the host chose
+// (longest rays first); each workgroup takes the next chunk from a counter until the
+// queue is exhausted, so a workgroup that drew short rays simply takes more chunks.
+constexpr int kChunkBlocks = 16;
+
+struct BatchQueue {
+    int32_t n;                              // members
+    int32_t member[kMaxBatch];              // member of queue slot s
+    int64_t first_chunk[kMaxBatch + 1];     // first chunk of slot s; [n] = total
+    int64_t nblocks[kMaxBatch];             // 256-thread blocks of slot s
+};
+
+struct BatchIO {
+    const float* in[kMaxBatch];
+    const float* inT[kMaxBatch];
+    float* out[kMaxBatch];
+};
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward_batch(const DevPlan* __restrict__ plans, BatchQueue q, BatchIO io,
+                                                           unsigned long long* __restrict__ counter)
+{
+    __shared__ unsigned long long s_chunk;
+    const int64_t total = q.first_chunk[q.n];
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t chunk = (int64_t)s_chunk;
+        __syncthreads();
+        if (chunk >= total) break;
+        int32_t s = 0;
+        while (s + 1 < q.n && chunk >= q.first_chunk[s + 1]) ++s;
+        const int32_t m = q.member[s];
+        const DevPlan& P = plans[m];
+        const int64_t blk0 = (chunk - q.first_chunk[s]) * kChunkBlocks;
+        for (int c = 0; c < kChunkBlocks; ++c) {
+            const int64_t blk = blk0 + c;
+            if (blk >= q.nblocks[s]) break;
+            const int32_t r = forward_ray_of<MODE>(P, (uint64_t)blk * kBlock + threadIdx.x);
+            if (r >= 0) forward_one<DIM, MODE>(P, r, io.in[m], io.inT[m], io.out[m]);
+        }
+    }
+}
+
+__global__ void k_reset_counter(unsigned long long* c)
+{
+    if (threadIdx.x == 0) *c = 0ull;
 }
 
 // out[z][x][y] = in[z][y][x]
@@ -263,23 +363,92 @@ xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s)
     return hip_fail(hipGetLastError(), "fill kernel launch");
 }
 
+xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, hipStream_t s)
+{
+    const int32_t ytiles = (P.ny + 31) / 32;
+    hipLaunchKernelGGL(k_transpose_xy, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ytiles * P.nz)), dim3(kBlock), 0,
+                       s, img, imgT, P.nx, P.ny, ytiles);
+    return hip_fail(hipGetLastError(), "transpose launch");
+}
+
 xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s)
 {
     const DevPlan& P = p->dp;
+    const uint64_t nb64 = (forward_threads(P) + kBlock - 1) / kBlock;
+    if (nb64 > 0x7FFFFFF0ull) { set_error("forward launch too large"); return XRT_E_SIZE; }
+    const uint32_t nb = (uint32_t)nb64;
+    const uint32_t grid = P.xcd_remap ? (nb + 7u) / 8u * 8u : nb;
     if (p->d_imgT == nullptr)
-        return dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, (const float*)nullptr, sino);
-    const int32_t ytiles = (P.ny + 31) / 32;
+        return dispatch<FwdK>(P, dim3(grid, (unsigned)batch), s, img, (const float*)nullptr, sino, nb);
     for (int b = 0; b < batch; ++b) {
         const float* im = img + (int64_t)b * P.n_units;
-        hipLaunchKernelGGL(k_transpose_xy, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ytiles * P.nz)), dim3(kBlock),
-                           0, s, im, p->d_imgT, P.nx, P.ny, ytiles);
-        xrt_status st = hip_fail(hipGetLastError(), "transpose launch");
+        xrt_status st = launch_transpose_xy(P, im, p->d_imgT, s);
         if (st != XRT_OK) return st;
-        st = dispatch<FwdK>(P, dim3(blocks_for(P.n_rays), 1u), s, im, (const float*)p->d_imgT,
-                            sino + (int64_t)b * P.n_rays);
+        st = dispatch<FwdK>(P, dim3(grid, 1u), s, im, (const float*)p->d_imgT, sino + (int64_t)b * P.n_rays, nb);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;
+}
+
+xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const DevPlan* d_plans, int32_t n,
+                                const int32_t* order, const float* const* imgs, float* const* sinos,
+                                unsigned long long* counter, uint32_t grid, hipStream_t s)
+{
+    BatchQueue q{};
+    BatchIO io{};
+    q.n = n;
+    int64_t chunk = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t m = order[k];
+        const uint64_t nb = (forward_threads(hp[m]) + kBlock - 1) / kBlock;
+        q.member[k] = m;
+        q.first_chunk[k] = chunk;
+        q.nblocks[k] = (int64_t)nb;
+        chunk += ((int64_t)nb + kChunkBlocks - 1) / kChunkBlocks;
+    }
+    q.first_chunk[n] = chunk;
+    for (int32_t m = 0; m < n; ++m) {
+        io.in[m] = imgs[m];
+        io.out[m] = sinos[m];
+        io.inT[m] = imgT[m];
+        if (imgT[m]) {
+            xrt_status st = launch_transpose_xy(hp[m], imgs[m], imgT[m], s);
+            if (st != XRT_OK) return st;
+        }
+    }
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    xrt_status st = hip_fail(hipGetLastError(), "counter reset launch");
+    if (st != XRT_OK) return st;
+    const DevPlan& P0 = hp[0];
+    if ((int64_t)grid > chunk) grid = (uint32_t)chunk;
+    if (grid == 0) return XRT_OK;
+    if (P0.dim == 3 && P0.mode == MODE_DIVERGENT)
+        hipLaunchKernelGGL((k_forward_batch<3, MODE_DIVERGENT>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else if (P0.dim == 3 && P0.mode == MODE_PARALLEL)
+        hipLaunchKernelGGL((k_forward_batch<3, MODE_PARALLEL>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else if (P0.dim == 3 && P0.mode == MODE_ARC)
+        hipLaunchKernelGGL((k_forward_batch<3, MODE_ARC>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else if (P0.dim == 2 && P0.mode == MODE_DIVERGENT)
+        hipLaunchKernelGGL((k_forward_batch<2, MODE_DIVERGENT>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else if (P0.dim == 2 && P0.mode == MODE_PARALLEL)
+        hipLaunchKernelGGL((k_forward_batch<2, MODE_PARALLEL>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else if (P0.dim == 2 && P0.mode == MODE_ARC)
+        hipLaunchKernelGGL((k_forward_batch<2, MODE_ARC>), dim3(grid), dim3(kBlock), 0, s, d_plans, q, io, counter);
+    else {
+        set_error("batched projection of ray lists is not supported");
+        return XRT_E_UNSUPPORTED;
+    }
+    return hip_fail(hipGetLastError(), "batched forward launch");
+}
+
+uint32_t forward_batch_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_forward_batch<3, MODE_DIVERGENT>, kBlock, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 4;
+    }
+    return nb > 0 ? (uint32_t)nb : 1u;
 }
 
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,

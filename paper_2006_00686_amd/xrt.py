@@ -43,6 +43,10 @@ class Scan(ctypes.Structure):
                 ("ray_params", _dp), ("n_rays", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("packet_cols", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
 _LIB = None
 
 
@@ -72,6 +76,12 @@ def _lib():
         lib.xrt_conv3x3_wgrad_workspace.restype = i64
         lib.xrt_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, i64, vp, vp]
         lib.xrt_precond_apply.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        lib.xrt_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        lib.xrt_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        lib.xrt_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+        lib.xrt_batch_destroy.argtypes = [vp]
+        lib.xrt_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        lib.xrt_batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
                   "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
                   "xrt_vec_xpby_ratio", "xrt_vec_axpby", "xrt_conv3x3", "xrt_conv3x3_wgrad"):
@@ -175,6 +185,18 @@ class Plan:
     def handle(self):
         return self._h
 
+    # -------------------------------------------------------------- launch shape
+
+    def set_tuning(self, packet_cols: int = 0, xcd_remap: int = 0):
+        """Forward launch shape (see xrt_tuning); results do not depend on it."""
+        t = Tuning(int(packet_cols), int(xcd_remap))
+        _check(_lib().xrt_plan_set_tuning(self._h, ctypes.byref(t)), "xrt_plan_set_tuning")
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(_lib().xrt_plan_get_tuning(self._h, ctypes.byref(t)), "xrt_plan_get_tuning")
+        return {"packet_cols": t.packet_cols, "xcd_remap": t.xcd_remap}
+
     # -------------------------------------------------------------- operators
 
     def _batch(self, t: torch.Tensor, inner):
@@ -228,6 +250,58 @@ class Plan:
         _check(_lib().xrt_ray_hits(self._h, first, n, eps, _ptr(offs), _ptr(idx), _ptr(ln), _stream(self.device)),
                "xrt_ray_hits")
         return offs, idx[:total], ln[:total]
+
+
+class Batch:
+    """Several plans projected together: the forward of all members is one persistent
+    launch (longest rays first); no allocation or synchronisation happens in forward /
+    adjoint, so both can be captured in a graph.  Keeps references to its plans."""
+
+    def __init__(self, plans: list):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(_lib().xrt_batch_create(arr, len(self.plans), ctypes.byref(h)), "xrt_batch_create")
+        self._h = h
+        self.device = self.plans[0].device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().xrt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, shapes):
+        if len(ts) != len(self.plans):
+            raise ValueError(f"expected {len(self.plans)} tensors, got {len(ts)}")
+        for t, shp, p in zip(ts, shapes, self.plans):
+            p._dev_check(t)
+            if tuple(t.shape) != tuple(shp):
+                raise ValueError(f"expected shape {tuple(shp)}, got {tuple(t.shape)}")
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def forward(self, imgs: list, out: list | None = None) -> list:
+        if out is None:
+            out = [torch.empty(tuple(p.sino_shape), dtype=torch.float32, device=f"cuda:{p.device}")
+                   for p in self.plans]
+        a = self._ptrs(imgs, [p.image_shape for p in self.plans])
+        b = self._ptrs(out, [p.sino_shape for p in self.plans])
+        _check(_lib().xrt_batch_forward(self._h, a, b, _stream(self.device)), "xrt_batch_forward")
+        return out
+
+    def adjoint(self, sinos: list, mode: str = "auto", out: list | None = None) -> list:
+        if out is None:
+            out = [torch.empty(tuple(p.image_shape), dtype=torch.float32, device=f"cuda:{p.device}")
+                   for p in self.plans]
+        a = self._ptrs(sinos, [p.sino_shape for p in self.plans])
+        b = self._ptrs(out, [p.image_shape for p in self.plans])
+        _check(_lib().xrt_batch_adjoint(self._h, a, b, ADJ[mode], _stream(self.device)), "xrt_batch_adjoint")
+        return out
 
 
 # ------------------------------------------------------------------ batched vector kernels
