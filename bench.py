@@ -97,6 +97,51 @@ def learned_solve(torch, dev, tol: float = 1e-3):
             "weights": os.path.relpath(learned.default_weights(), ROOT)}
 
 
+def batched_bench(torch, dev, steps: int, tuning: dict):
+    """16 uneven cone / helical problems: forward of all members in one persistent launch
+    plus every member's adjoint, captured once in a graph and replayed; the same work as
+    plain per-plan launches for comparison."""
+    from paper_2006_00686_amd import inputs, xrt
+    from paper_2006_00686_amd.batched import BatchGraph
+    cfg = inputs.batched_config()
+    plans = [xrt.Plan(m["grid"], m["scan"], 0) for m in cfg["members"]]
+    for p in plans:
+        p.set_tuning(**tuning)
+    bg = BatchGraph(xrt.Batch(plans))
+    gen = torch.Generator(device=dev)
+    for k, im in enumerate(bg.imgs):
+        gen.manual_seed(cfg["members"][k]["seed"])
+        im.uniform_(0.0, 1.0, generator=gen)
+    bg.capture()
+    bg.replay()
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_graph = timed(bg.replay)
+
+    def eager():
+        for p, im, sn, bk in zip(plans, bg.imgs, bg.sinos, bg.backs):
+            p.forward(im, out=sn)
+            p.adjoint(sn, out=bk)
+
+    eager()
+    t_eager = timed(eager)
+    rays = sum(p.n_rays for p in plans)
+    dims = sorted({tuple(p.image_shape) for p in plans}, key=lambda d: -int(np.prod(d)))
+    return {"workload": cfg["name"], "members": len(plans), "rays": rays, "volumes_zyx": [list(d) for d in dims],
+            "ms_per_step": round(t_graph, 3), "mrays_per_s": round(rays / (t_graph * 1e-3) / 1e6, 1),
+            "per_plan_launches_ms": round(t_eager, 3), "launch": tuning,
+            "data": "synthetic: seeded uniform volumes"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +150,8 @@ def main():
     ap.add_argument("--adjoint", default="auto", choices=["auto", "scatter", "gather"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched launch")
+    ap.add_argument("--no-tune", action="store_true", help="default forward launch shape instead of the autotuner")
     ap.add_argument("--cpu-views-every", type=int, default=15)
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -131,6 +178,13 @@ def main():
     nnz = int(plan.hit_counts(eps=1e-9).to(torch.int64).sum().item())
     M, V = plan.n_rays, plan.n_units
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
+
+    tuning = {"packet_cols": 0, "xcd_remap": 0}
+    if not args.no_tune:
+        from paper_2006_00686_amd import tune
+        res = tune.autotune(plan, d_img, log=log)
+        tuning = {"packet_cols": res["packet_cols"], "xcd_remap": res["xcd_remap"]}
+        log(f"[bench] forward launch shape {tuning} ({'cached' if res['cached'] else 'tuned'})")
 
     if args.copy_reference:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -176,6 +230,12 @@ def main():
                 "fwd_ms": round(t_fwd, 4), "adj_ms": round(t_adj, 4),
                 "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    batched = None
+    if not args.no_batched:
+        log("[bench] batched launch: 16 uneven cone/helical problems")
+        batched = batched_bench(torch, dev, 3, tuning)
+        log(f"[bench] batched {batched}")
+
     learned = None
     if not args.no_learned:
         log("[bench] learned preconditioner vs plain CGLS (sparse-view fan beam, batch 64)")
@@ -205,10 +265,11 @@ def main():
         "config": {"workload": cfg["name"], "volume": [256, 256, 256], "views": 360, "detector": [384, 512],
                    "sod": 1000.0, "sdd": 1500.0, "rays": M, "nnz": nnz, "adjoint": args.adjoint,
                    "intersections_per_s": round(2 * nnz / (ms_step * 1e-3), 1),
-                   "crossing_parameter_dtype": "f64", "parallelism": "single GPU"},
+                   "crossing_parameter_dtype": "f64", "parallelism": "single GPU", "launch": tuning},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "learned": learned,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -105,7 +105,10 @@ constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
 // One wave per voxel column (i, j) and z chunk; lane = voxel along z, KB per lane.
 // NR: bound on the rows a voxel's shadow covers in one detector column (from the plan).
 // ZR: the detector has a row with v = 0, whose rays lie in the plane z = Sz.
-template <int KB, int NR, bool ZR>
+// CULL (helical scans, where the detector sees a band of z at a time): a wave skips a
+// block of 64 voxels when none of them has a candidate row on the detector; skipped
+// rows are exactly the ones that would add nothing.
+template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
                                                          float* __restrict__ img,
                                                          const double* __restrict__ inv_v, int32_t zero_row,
@@ -181,6 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
                 // rows outside the voxel's range fail C_low < C_up below on their own
                 // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
                 const int32_t r0 = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
+                if constexpr (CULL) {
+                    // rows past the detector are zero padding; a voxel whose rows all lie
+                    // above the first row (by half a bin, far beyond the error of the
+                    // estimates) has no hit in rows r0 = 0 ..
+                    const double vtop = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                    const bool live = k < P.nz && r0 < P.n_rows && vtop >= -0.5;
+                    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
+                }
                 auto row = [&](int e, double& l, float& g) {
                     const int32_t r = r0 + e;
                     double lo = tin, hi = tout;
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __r
         if (b0 + q < batch) img[(int64_t)(b0 + q) * P.n_units + pix] = (float)acc[q];
 }
 
-template <int KB, int NR>
+template <int KB, int NR, bool CULL>
 xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
 {
     const DevPlan& P = p->dp;
@@ -317,22 +328,28 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
     const int64_t launched = (nlog + 7) / 8 * 8;
     const size_t lds = (size_t)(P.n_rows + NR) * sizeof(double);
     if (p->zero_row >= 0)
-        hipLaunchKernelGGL((k_cone_gather<KB, NR, true>), dim3((unsigned)launched), dim3(kBlock), lds, s, P, gT,
-                           img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+        hipLaunchKernelGGL((k_cone_gather<KB, NR, true, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
     else
-        hipLaunchKernelGGL((k_cone_gather<KB, NR, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P, gT,
-                           img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+        hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
     return hip_fail(hipGetLastError(), "gather kernel launch");
+}
+
+template <int NR, bool CULL>
+xrt_status launch_nr_c(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
+{
+    const int32_t nz = p->dp.nz;
+    if (nz <= 64) return launch_kb<1, NR, CULL>(p, gT, img, s);
+    if (nz <= 128) return launch_kb<2, NR, CULL>(p, gT, img, s);
+    if (nz <= 256) return launch_kb<4, NR, CULL>(p, gT, img, s);
+    return launch_kb<8, NR, CULL>(p, gT, img, s);
 }
 
 template <int NR>
 xrt_status launch_nr(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
 {
-    const int32_t nz = p->dp.nz;
-    if (nz <= 64) return launch_kb<1, NR>(p, gT, img, s);
-    if (nz <= 128) return launch_kb<2, NR>(p, gT, img, s);
-    if (nz <= 256) return launch_kb<4, NR>(p, gT, img, s);
-    return launch_kb<8, NR>(p, gT, img, s);
+    return p->helical ? launch_nr_c<NR, true>(p, gT, img, s) : launch_nr_c<NR, false>(p, gT, img, s);
 }
 
 }  // namespace
@@ -373,7 +390,9 @@ xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, floa
         float* out = img + (int64_t)b * P.n_units;
         if (p->gather_nr <= 2) st = launch_nr<2>(p, p->d_gT, out, s);
         else if (p->gather_nr == 3) st = launch_nr<3>(p, p->d_gT, out, s);
-        else st = launch_nr<4>(p, p->d_gT, out, s);
+        else if (p->gather_nr == 4) st = launch_nr<4>(p, p->d_gT, out, s);
+        else if (p->gather_nr <= 6) st = launch_nr<6>(p, p->d_gT, out, s);
+        else st = launch_nr<8>(p, p->d_gT, out, s);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;

@@ -307,6 +307,8 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
 {
     const DevPlan& D = p->dp;
     p->zero_row = -1;
+    p->helical = 0;
+    for (const ViewGeom& V : views) p->helical |= V.A[2] != views[0].A[2] ? 1 : 0;
     // The detector columns that see a pixel are the interval between its corners' u
     // coordinates only when the pixel is in front of the source; require it of the
     // whole image box for every view, otherwise the plan uses the scatter adjoint.
@@ -344,7 +346,7 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
         const double spread = rho * (D.pdz / hmin + zrel * diag / (hmin * hmin)) / D.dv;
         const double nr = std::floor(spread + 1e-6) + 1.0;
         // the 1/v table of the rows lives in LDS (at most 32 KiB)
-        if (!(hmin > 0.0) || !(nr <= 4.0) || D.n_rows + 4 > 4096) {
+        if (!(hmin > 0.0) || !(nr <= 8.0) || D.n_rows + 8 > 4096) {
             p->gather_ok = 0;
             return XRT_OK;
         }
