@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched launch")
-    ap.add_argument("--no-tune", action="store_true", help="default forward launch shape instead of the autotuner")
+    ap.add_argument("--tune", action="store_true", help="autotune the forward launch shape first (else the default)")
     ap.add_argument("--cpu-views-every", type=int, default=15)
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -180,7 +180,7 @@ def main():
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
 
     tuning = {"packet_cols": 0, "xcd_remap": 0}
-    if not args.no_tune:
+    if args.tune:
         from paper_2006_00686_amd import tune
         res = tune.autotune(plan, d_img, log=log)
         tuning = {"packet_cols": res["packet_cols"], "xcd_remap": res["xcd_remap"]}
