@@ -17,7 +17,8 @@ constexpr int kBlock = 256;
 // Forward: gathers are hardware-bounds-checked buffer loads on byte offsets.  A
 // candidate that is not hit is pointed out of range, so its load returns 0 without a
 // memory access and its (finite) length adds nothing; the loads of a slab are issued
-// together.
+// together, and the slab's products are summed one slab later, so that the loads'
+// latency overlaps the next slab's arithmetic (the order of the sum is unchanged).
 constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
 
 __device__ __forceinline__ const float* uniform_ptr(const float* p)
@@ -28,23 +29,42 @@ __device__ __forceinline__ const float* uniform_ptr(const float* p)
     return (const float*)(((uint64_t)hi << 32) | lo);
 }
 
+// Buffer resource of a wave-uniform image (base and size taken from the first lane).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const float* img, int32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)uniform_ptr(img), (short)0, __builtin_amdgcn_readfirstlane(nbytes),
+                                             0x00020000);
+}
+
 struct FwdVisit {
     static constexpr int32_t kIndexScale = 4;
-    const float* img;    // wave-uniform base of one image
-    int32_t nbytes;      // wave-uniform size of the image in bytes
+    __amdgpu_buffer_rsrc_t rsrc;   // the image (built once per ray, outside the walk)
     double acc;
+    // the previous slab's loaded values and lengths, consumed after this slab's loads
+    // are issued (their latency overlaps the next slab's arithmetic)
+    float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+    double q1 = 0.0, q2 = 0.0, q3 = 0.0;
     __device__ __forceinline__ float load(int32_t off)
     {
-        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)uniform_ptr(img), (short)0, __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+    }
+    __device__ __forceinline__ void consume()
+    {
+        acc = fma((double)p1, q1, acc);
+        acc = fma((double)p2, q2, acc);
+        acc = fma((double)p3, q3, acc);
     }
     __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
     {
         const float f1 = load(I1);
         const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
-        acc = fma((double)f1, l1, acc);
-        acc = fma((double)f2, l2, acc);
+        consume();
+        p1 = f1;
+        p2 = f2;
+        p3 = 0.0f;
+        q1 = l1;
+        q2 = l2;
+        q3 = 0.0;
     }
     __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
                                           double l3)
@@ -52,9 +72,13 @@ struct FwdVisit {
         const float f1 = load(I1);
         const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
         const float f3 = load(l3 > 0.0 ? I3 : kOutOfRange);
-        acc = fma((double)f1, l1, acc);
-        acc = fma((double)f2, l2, acc);
-        acc = fma((double)f3, l3, acc);
+        consume();
+        p1 = f1;
+        p2 = f2;
+        p3 = f3;
+        q1 = l1;
+        q2 = l2;
+        q3 = l3;
     }
 };
 
@@ -178,8 +202,9 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
             }
         }
     }
-    FwdVisit v{base, (int32_t)(P.n_units * 4), 0.0};
+    FwdVisit v{image_rsrc(base, (int32_t)(P.n_units * 4)), 0.0};
     walk<DIM>(P, R, v);
+    v.consume();
     sino[r] = (float)(v.acc * R.scale);
 }
 

@@ -277,15 +277,16 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
         const double dt1 = ax[1].w != 0.0 ? fabs(inv1) : kNone;
         const double e1 = dt1 - dt0;
         double r1 = fmax(tn1 - tx0, 0.0);
+        const double r1s = r1;
         int32_t n1 = 0;
         if constexpr (DIM == 2) {
+#pragma unroll 2
             for (int32_t s = nint; s > 0; --s) {
                 const double l1 = fmin(r1, dt0);
                 const double l2 = dt0 - r1;
                 const bool c1 = r1 < dt0;
                 const int32_t Iend = c1 ? I + sd1 : I;
                 vis.two(I, l1, Iend, l2);
-                n1 += c1;
                 r1 += c1 ? e1 : -dt0;
                 I = Iend + sd0;
             }
@@ -293,7 +294,8 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
             const double dt2 = ax[2].w != 0.0 ? fabs(inv2) : kNone;
             const double e2 = dt2 - dt0;
             double r2 = fmax(tn2 - tx0, 0.0);
-            int32_t n2 = 0;
+            const double r2s = r2;
+#pragma unroll 2
             for (int32_t s = nint; s > 0; --s) {
                 const double a = fmin(r1, r2), b = fmax(r1, r2);
                 const double l1 = fmin(a, dt0);
@@ -303,17 +305,21 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                 const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
                 const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
                 vis.three(I, l1, Imid, l2, Iend, l3);
-                n1 += c1;
-                n2 += c2;
                 r1 += c1 ? e1 : -dt0;
                 r2 += c2 ? e2 : -dt0;
                 I = Iend + sd0;
             }
+            // crossings taken along the second secondary axis (see n1 below)
+            const int32_t n2 = (int32_t)rint((r2 - r2s + (double)nint * dt0) / dt2);
             if (n2 > 0) {
                 m2 += sg2 * (double)n2;
                 tn2 = (m2 - q2) * inv2;
             }
         }
+        // crossings taken along the first secondary axis: every slab moved r by -dt0 and
+        // every crossing added dt1 (r - r_start + nint dt0 = n dt1, up to rounding far
+        // below dt1 / 2; an axis without crossings keeps r = 1e300 and gives n = 0)
+        n1 = (int32_t)rint((r1 - r1s + (double)nint * dt0) / dt1);
         if (n1 > 0) {
             m1 += sg1 * (double)n1;
             tn1 = (m1 - q1) * inv1;
