@@ -204,7 +204,9 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
                         hi = fmin(hi, fmax(t0, t1));
                     }
                     const bool hit = hi > lo && k < P.nz;   // C_low < C_up
-                    l = hit ? hi - lo : 0.0;
+                    // a candidate that is not hit reads 0 (out of range): its (finite,
+                    // non-positive) length then adds nothing
+                    l = hi - lo;
                     g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                                                       gsrc, hit ? gcol4 + 4 * r : kOutOfRange, 0, 0));
                 };
