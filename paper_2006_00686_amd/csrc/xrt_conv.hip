@@ -313,12 +313,12 @@ static_assert(kH2C == 32 && kH2R == 4 * (kPB / 64), "one 32-pixel row per MFMA t
 static_assert(9 * kH2R * kH2C * 4 <= kH1N * kH1S * 2, "tap partials fit in the h1 buffer");
 
 template <bool TR>
-__global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, const float* __restrict__ Wa,
+__global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k_precond(const float* __restrict__ x, const float* __restrict__ Wa,
                                                   const float* __restrict__ Wb, const float* __restrict__ Wc,
                                                   float* __restrict__ y, int32_t H, int32_t Wd, int32_t tiles_x,
                                                   int32_t tiles_y, int64_t ntiles)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sx[kXR * kXC];
+    __shared__ float sx[kXR * kXC];   // x on the ring (FP32: also the residual)
     __shared__ __attribute__((aligned(16))) __bf16 sh1[kH1N * kH1S];
     float* su = (float*)sh1;   // tap partials [9][kH2R][kH2C], after C2 has read h1
 
@@ -342,19 +342,39 @@ __global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, co
             a3[st][e] = (__bf16)(m < 9 ? wload(Wc, TR, 0, m, c, 32, 1) : 0.0f);
         }
 
+    // x on the three-pixel ring of a tile (zero outside the image), three values per
+    // thread, loaded into registers one tile ahead so that the global loads of the next
+    // tile are in flight while this one computes
+    constexpr int kXPer = (kXR * kXC + kPB - 1) / kPB;
+    float xr[kXPer];
+    auto load_ring = [&](int64_t t) {
+        const int32_t X0 = (int32_t)(t % tiles_x) * kTW;
+        const int64_t rest = t / tiles_x;
+        const int32_t Y0 = (int32_t)(rest % tiles_y) * kTH;
+        const int64_t im = (rest / tiles_y) * (int64_t)H * Wd;
+#pragma unroll
+        for (int j = 0; j < kXPer; ++j) {
+            const int k = threadIdx.x + j * kPB;
+            const int32_t iy = Y0 - 3 + k / kXC, ix = X0 - 3 + k % kXC;
+            const bool in = k < kXR * kXC && iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+            xr[j] = in ? x[im + (int64_t)iy * Wd + ix] : 0.0f;
+        }
+    };
+    if (blockIdx.x < ntiles) load_ring(blockIdx.x);
+
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int32_t tx = (int32_t)(tile % tiles_x);
         const int64_t rest = tile / tiles_x;
         const int32_t ty = (int32_t)(rest % tiles_y);
         const int64_t img = (rest / tiles_y) * (int64_t)H * Wd;
         const int32_t X0 = tx * kTW, Y0 = ty * kTH;
-        // x on the three-pixel ring, zero outside the image
-        for (int k = threadIdx.x; k < kXR * kXC; k += kPB) {
-            const int32_t iy = Y0 - 3 + k / kXC, ix = X0 - 3 + k % kXC;
-            const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
-            sx[k] = (__bf16)(in ? x[img + (int64_t)iy * Wd + ix] : 0.0f);
+#pragma unroll
+        for (int j = 0; j < kXPer; ++j) {
+            const int k = threadIdx.x + j * kPB;
+            if (k < kXR * kXC) sx[k] = xr[j];
         }
         __syncthreads();
+        if (tile + gridDim.x < ntiles) load_ring(tile + gridDim.x);
         // C1 on the h1 region (pixels P = 32 T + m, row P / kH1C, column P % kH1C)
         for (int T = wv; T < kH1Tiles; T += kPB / 64) {
             const int32_t P = T * 32 + m, pr = P / kH1C, pc = P % kH1C;
@@ -363,7 +383,7 @@ __global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, co
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int t = kb * 8 + e;
-                bx[e] = (valid && t < 9) ? sx[(pr + t / 3) * kXC + pc + t % 3] : (__bf16)0.0f;
+                bx[e] = (__bf16)((valid && t < 9) ? sx[(pr + t / 3) * kXC + pc + t % 3] : 0.0f);
             }
             const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bx, f32x16{}, 0, 0, 0);
             if (valid) {
@@ -379,20 +399,20 @@ __global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, co
             }
         }
         __syncthreads();
-        // C2: h2 region rows R = wv + 4 j, column m
+        // C2: h2 region rows R = wv + 4 j, column m; the four rows' accumulations are
+        // interleaved (independent MFMA chains)
         f32x16 h2[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t R = wv + 4 * j;
-            f32x16 acc = {};
+        for (int j = 0; j < 4; ++j) h2[j] = f32x16{};
 #pragma unroll
-            for (int st = 0; st < 18; ++st) {
-                const int t = st >> 1;
-                const bf16x8 b =
-                    *(const bf16x8*)&sh1[((R + t / 3) * kH1C + m + t % 3) * kH1S + (st & 1) * 16 + kb * 8];
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[st], b, acc, 0, 0, 0);
-            }
-            h2[j] = acc;
+        for (int st = 0; st < 18; ++st) {
+            const int t = st >> 1;
+            bf16x8 b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[j] = *(const bf16x8*)&sh1[((wv + 4 * j + t / 3) * kH1C + m + t % 3) * kH1S + (st & 1) * 16 + kb * 8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[st], b[j], h2[j], 0, 0, 0);
         }
         __syncthreads();
         // C3 tap partials into LDS (h2 zero outside the image)
@@ -421,8 +441,7 @@ __global__ __launch_bounds__(kPB) void k_precond(const float* __restrict__ x, co
                 float sum = 0.0f;
 #pragma unroll
                 for (int t = 0; t < 9; ++t) sum += su[(t * kH2R + r + t / 3) * kH2C + c + t % 3];
-                const int64_t o = img + (int64_t)iy * Wd + ix;
-                y[o] = x[o] + sum;
+                y[img + (int64_t)iy * Wd + ix] = sx[(r + 3) * kXC + c + 3] + sum;
             }
         }
         __syncthreads();
@@ -494,7 +513,16 @@ xrt_status xrt_precond_apply(int32_t transposed, int32_t batch, int32_t height, 
     }
     const int32_t tiles_x = (width + kTW - 1) / kTW, tiles_y = (height + kTH - 1) / kTH;
     const int64_t ntiles = (int64_t)batch * tiles_x * tiles_y;
-    const unsigned grid = (unsigned)(ntiles < 2048 ? ntiles : 2048);
+    // persistent workgroups, two per CU (the LDS and registers of one allow two)
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    const int64_t want = 2 * (int64_t)cus;
+    const unsigned grid = (unsigned)(ntiles < want ? ntiles : want);
     hipStream_t s = (hipStream_t)stream;
     if (transposed)
         hipLaunchKernelGGL(k_precond<true>, dim3(grid), dim3(kPB), 0, s, d_x, d_w3, d_w2, d_w1, d_y, height, width,
