@@ -315,8 +315,8 @@ static_assert(9 * kH2R * kH2C * 4 <= kH1N * kH1S * 2, "tap partials fit in the h
 template <bool TR>
 __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k_precond(const float* __restrict__ x, const float* __restrict__ Wa,
                                                   const float* __restrict__ Wb, const float* __restrict__ Wc,
-                                                  float* __restrict__ y, int32_t H, int32_t Wd, int32_t tiles_x,
-                                                  int32_t tiles_y, int64_t ntiles)
+                                                  float* __restrict__ y, int32_t H, int32_t Wd, uint32_t tiles_x,
+                                                  uint32_t tiles_y, uint32_t ntiles)
 {
     __shared__ float sx[kXR * kXC];   // x on the ring (FP32: also the residual)
     __shared__ __attribute__((aligned(16))) __bf16 sh1[kH1N * kH1S];
@@ -347,11 +347,13 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     // tile are in flight while this one computes
     constexpr int kXPer = (kXR * kXC + kPB - 1) / kPB;
     float xr[kXPer];
-    auto load_ring = [&](int64_t t) {
-        const int32_t X0 = (int32_t)(t % tiles_x) * kTW;
-        const int64_t rest = t / tiles_x;
-        const int32_t Y0 = (int32_t)(rest % tiles_y) * kTH;
-        const int64_t im = (rest / tiles_y) * (int64_t)H * Wd;
+    // tile index -> (column, row, image): 32-bit divisions of a wave-uniform value
+    auto load_ring = [&](uint32_t t) {
+        const uint32_t rest = t / tiles_x;
+        const int32_t X0 = (int32_t)(t - rest * tiles_x) * kTW;
+        const uint32_t bi = rest / tiles_y;
+        const int32_t Y0 = (int32_t)(rest - bi * tiles_y) * kTH;
+        const int64_t im = (int64_t)bi * H * Wd;
 #pragma unroll
         for (int j = 0; j < kXPer; ++j) {
             const int k = threadIdx.x + j * kPB;
@@ -362,12 +364,12 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     };
     if (blockIdx.x < ntiles) load_ring(blockIdx.x);
 
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int32_t tx = (int32_t)(tile % tiles_x);
-        const int64_t rest = tile / tiles_x;
-        const int32_t ty = (int32_t)(rest % tiles_y);
-        const int64_t img = (rest / tiles_y) * (int64_t)H * Wd;
-        const int32_t X0 = tx * kTW, Y0 = ty * kTH;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t rest = tile / tiles_x;
+        const int32_t X0 = (int32_t)(tile - rest * tiles_x) * kTW;
+        const uint32_t bi = rest / tiles_y;
+        const int32_t Y0 = (int32_t)(rest - bi * tiles_y) * kTH;
+        const int64_t img = (int64_t)bi * H * Wd;
 #pragma unroll
         for (int j = 0; j < kXPer; ++j) {
             const int k = threadIdx.x + j * kPB;
@@ -513,6 +515,10 @@ xrt_status xrt_precond_apply(int32_t transposed, int32_t batch, int32_t height, 
     }
     const int32_t tiles_x = (width + kTW - 1) / kTW, tiles_y = (height + kTH - 1) / kTH;
     const int64_t ntiles = (int64_t)batch * tiles_x * tiles_y;
+    if (ntiles >= ((int64_t)1 << 31)) {
+        set_error("xrt_precond_apply: too many tiles (batch x height x width too large)");
+        return XRT_E_SIZE;
+    }
     // persistent workgroups, two per CU (the LDS and registers of one allow two)
     int cus = 256;
     int dev = 0;
@@ -526,10 +532,10 @@ xrt_status xrt_precond_apply(int32_t transposed, int32_t batch, int32_t height, 
     hipStream_t s = (hipStream_t)stream;
     if (transposed)
         hipLaunchKernelGGL(k_precond<true>, dim3(grid), dim3(kPB), 0, s, d_x, d_w3, d_w2, d_w1, d_y, height, width,
-                           tiles_x, tiles_y, ntiles);
+                           (uint32_t)tiles_x, (uint32_t)tiles_y, (uint32_t)ntiles);
     else
         hipLaunchKernelGGL(k_precond<false>, dim3(grid), dim3(kPB), 0, s, d_x, d_w1, d_w2, d_w3, d_y, height, width,
-                           tiles_x, tiles_y, ntiles);
+                           (uint32_t)tiles_x, (uint32_t)tiles_y, (uint32_t)ntiles);
     return hip_fail(hipGetLastError(), "xrt_precond_apply launch");
 }
 
