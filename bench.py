@@ -78,7 +78,7 @@ def learned_solve(torch, dev, tol: float = 1e-3):
     wall time to relative residual `tol` of plain CGLS and of CGLS right-preconditioned by
     the trained CNN, plus the true data residual of both final images."""
     from paper_2006_00686_amd import inputs, learned, xrt
-    cfg = inputs.config(5)
+    cfg = inputs.workload("fan2d_256_sparse")
     plan = xrt.Plan(cfg["grid"], cfg["scan"], 0)
     g = learned.training_batch(cfg, plan, cfg["batch"], learned.EVAL_SEED0, dev)
     P = learned.ConvPreconditioner(dev).load(learned.default_weights())
@@ -103,7 +103,7 @@ def batched_bench(torch, dev, steps: int, tuning: dict):
     plain per-plan launches for comparison."""
     from paper_2006_00686_amd import inputs, xrt
     from paper_2006_00686_amd.batched import BatchGraph
-    cfg = inputs.batched_config()
+    cfg = inputs.batched_workload()
     plans = [xrt.Plan(m["grid"], m["scan"], 0) for m in cfg["members"]]
     for p in plans:
         p.set_tuning(**tuning)
@@ -166,7 +166,7 @@ def main():
     from paper_2006_00686_amd import inputs
     from paper_2006_00686_amd import xrt
 
-    cfg = inputs.config(3)
+    cfg = inputs.workload("cone_256")
     log(f"[bench] building phantom {cfg['name']}")
     img = inputs.make_image(cfg)
     dev = torch.device("cuda:0")

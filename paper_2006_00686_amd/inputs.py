@@ -112,39 +112,51 @@ def helical_view_z(views_per_turn: int, turns: int, pitch: float, nrows: int, dv
     return -(turns * F) / 2.0 + F * k / views_per_turn
 
 
-def config(n: int) -> dict:
-    """Grid, scan and phantom recipe of workload n (1..5).  Phantoms are drawn by
-    make_image(cfg); the returned dict holds only parameters."""
-    if n == 1:
+WORKLOADS = ("par2d_128", "fan2d_512", "cone_256", "batched_cone_helical", "fan2d_256_sparse")
+
+
+def workload(name: str) -> dict:
+    """Grid, scan and phantom recipe of a named workload.  Phantoms are drawn by
+    make_image(cfg); the returned dict holds only parameters.
+
+    par2d_128: 128^2 unit pixels, 180 parallel views over [0, pi), 185 bins of 1.
+    fan2d_512: 512^2 pixels of 0.8 centred at (20, -15), 720 fan views over 2 pi, flat
+        detector of 1024 bins of 1.2, source-to-centre 1000, source-to-detector 1500.
+    cone_256: 256^3 unit voxels, 360 circular cone views over 2 pi, flat 384 x 512
+        detector of spacing 1, source-to-centre 1000, source-to-detector 1500.
+    batched_cone_helical: 16 uneven cone / helical problems (batched_workload()).
+    fan2d_256_sparse: 256^2 unit pixels, 60 fan views over 2 pi, 512 bins of 0.75,
+        batches of 64 phantoms with Poisson noise at 1e5 photons per ray."""
+    if name == "par2d_128":
         grid = dict(nx=128, ny=128, nz=0, dx=1.0, dy=1.0, cx=0.0, cy=0.0)
         scan = dict(kind="par2d", angles=np.arange(180) * np.pi / 180.0, ncols=185, du=1.0, u0=0.0)
         return dict(name="par2d_128_180x185", grid=grid, scan=scan, phantom=("ellipse", 10), seed=1)
-    if n == 2:
+    if name == "fan2d_512":
         grid = dict(nx=512, ny=512, nz=0, dx=0.8, dy=0.8, cx=20.0, cy=-15.0)
         scan = dict(kind="fan2d_flat", angles=np.arange(720) * 2 * np.pi / 720.0, ncols=1024, du=1.2,
                     u0=0.0, sod=1000.0, sdd=1500.0)
         return dict(name="fan2d_512_720x1024", grid=grid, scan=scan, phantom=("ellipse", 10), seed=2)
-    if n == 3:
+    if name == "cone_256":
         grid = dict(nx=256, ny=256, nz=256, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0)
         scan = dict(kind="cone_flat", angles=np.arange(360) * 2 * np.pi / 360.0, ncols=512, nrows=384,
                     du=1.0, dv=1.0, u0=0.0, v0=0.0, sod=1000.0, sdd=1500.0)
         return dict(name="cone_256^3_360x384x512", grid=grid, scan=scan, phantom=("ellipsoid", 20), seed=3)
-    if n == 5:
+    if name == "fan2d_256_sparse":
         grid = dict(nx=256, ny=256, nz=0, dx=1.0, dy=1.0, cx=0.0, cy=0.0)
         scan = dict(kind="fan2d_flat", angles=np.arange(60) * 2 * np.pi / 60.0, ncols=512, du=0.75,
                     u0=0.0, sod=1000.0, sdd=1500.0)
         return dict(name="fan2d_256_60x512_learned", grid=grid, scan=scan, phantom=("ellipse", 10),
                     seed=5, batch=64, photons=1e5)
-    if n == 4:
-        return batched_config()
-    raise ValueError(n)
+    if name == "batched_cone_helical":
+        return batched_workload()
+    raise ValueError(f"unknown workload {name!r} (known: {', '.join(WORKLOADS)})")
 
 
 BATCH_DIMS = [(64, 64, 64), (96, 96, 96), (128, 128, 64), (128, 128, 128), (192, 192, 128),
               (256, 256, 128), (256, 256, 256), (512, 512, 256)]
 
 
-def batched_config(count: int = 16, seed: int = 4, scale: float = 1.0) -> dict:
+def batched_workload(count: int = 16, seed: int = 4, scale: float = 1.0) -> dict:
     """Uneven batch: even members circular cone (512x384 flat detector, 360 views),
     odd members helical (pitch 1, 3 turns x 720 views, 768x64 detector).  Volume dims
     drawn from BATCH_DIMS; SOD ~ U[800, 1200], SDD/SOD ~ U[1.3, 1.7].  scale < 1

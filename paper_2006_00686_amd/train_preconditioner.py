@@ -36,7 +36,7 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     dev = "cuda:0"
-    cfg = inputs.config(5)
+    cfg = inputs.workload("fan2d_256_sparse")
     plan = X.Plan(cfg["grid"], cfg["scan"], device=0)
     t0 = time.perf_counter()
     P, hist = learned.train(plan, cfg, steps=args.steps, batch=args.batch, K=args.unroll, lr=args.lr,

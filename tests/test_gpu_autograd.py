@@ -55,7 +55,7 @@ def test_finite_difference_cone_256(ag):
     """256^3 cone of the benchmark: (L(f+ev) - L(f-ev)) / 2e = <grad L(f), v> for the
     quadratic L(f) = 1/2 ||A f - g||^2 (exact for any e up to rounding)."""
     _, xrt = ag
-    cfg = inputs.config(3)
+    cfg = inputs.workload("cone_256")
     dev = torch.device("cuda:0")
     plan = xrt.Plan(cfg["grid"], cfg["scan"])
     f = torch.from_numpy(inputs.make_image(cfg)).to(dev)

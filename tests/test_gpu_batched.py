@@ -60,7 +60,7 @@ def _close_adjoint(got, ref, msg):
 
 
 def _members(scale=0.12, count=6):
-    return inputs.batched_config(count=count, scale=scale)["members"]
+    return inputs.batched_workload(count=count, scale=scale)["members"]
 
 
 def test_batch_matches_each_plan(X):

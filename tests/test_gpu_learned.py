@@ -21,7 +21,7 @@ def env():
         pytest.skip("no GPU")
     from paper_2006_00686_amd import inputs, learned, solvers, xrt
     xrt.library()
-    cfg = inputs.config(5)
+    cfg = inputs.workload("fan2d_256_sparse")
     plan = xrt.Plan(cfg["grid"], cfg["scan"])
     g = learned.training_batch(cfg, plan, 16, learned.EVAL_SEED0, DEV)
     return dict(cfg=cfg, plan=plan, g=g, learned=learned, solvers=solvers)

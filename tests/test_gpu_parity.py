@@ -229,34 +229,34 @@ def test_geometry_errors_gpu(xrt):
 
 # ------------------------------------------------------------------ the workloads at full size
 
-def test_config1_full_parity(xrt):
-    cfg = inputs.config(1)
+def test_par2d_128_full_parity(xrt):
+    cfg = inputs.workload("par2d_128")
     img = inputs.make_image(cfg)
     plan = xrt.Plan(cfg["grid"], cfg["scan"])
     got = plan.forward(torch.from_numpy(img).to(dev())).cpu().numpy()
     ref, scl = H.forward_bar(cfg["grid"], cfg["scan"], img)
-    H.assert_within_bar(got, ref, scl, what="config 1 forward")
+    H.assert_within_bar(got, ref, scl, what="par2d_128 forward")
     adj = plan.adjoint(torch.from_numpy(got).to(dev())).cpu().numpy()
     aref, ascl = H.adjoint_bar(cfg["grid"], cfg["scan"], got)
-    H.assert_within_bar(adj, aref, ascl, what="config 1 adjoint")
+    H.assert_within_bar(adj, aref, ascl, what="par2d_128 adjoint")
     # the phi = 0 and phi = pi/2 views run exactly on grid lines: each sums the image once
     for v in (0, 90):
         assert abs(got[v].sum() - img.astype(np.float64).sum()) <= 1e-5 * np.abs(img).sum()
 
 
-def test_config2_full_parity(xrt):
-    cfg = inputs.config(2)
+def test_fan2d_512_full_parity(xrt):
+    cfg = inputs.workload("fan2d_512")
     img = inputs.make_image(cfg)
     plan = xrt.Plan(cfg["grid"], cfg["scan"])
     got = plan.forward(torch.from_numpy(img).to(dev())).cpu().numpy()
     ref, scl = H.forward_bar(cfg["grid"], cfg["scan"], img)
-    H.assert_within_bar(got, ref, scl, what="config 2 forward")
+    H.assert_within_bar(got, ref, scl, what="fan2d_512 forward")
 
 
-def test_config3_sampled_parity(xrt):
+def test_cone_256_sampled_parity(xrt):
     """256^3 cone, the benchmark's launch: sampled rays against the oracle, chord and
     adjoint identities over everything."""
-    cfg = inputs.config(3)
+    cfg = inputs.workload("cone_256")
     img = inputs.make_image(cfg)
     plan = xrt.Plan(cfg["grid"], cfg["scan"])
     dimg = torch.from_numpy(img).to(dev())
@@ -266,7 +266,7 @@ def test_config3_sampled_parity(xrt):
     p, th = ogeom.expand(cfg["scan"])
     ref = ocore.forward_lines(cfg["grid"], p[sample], th[sample], img.astype(np.float64))
     scl = ocore.forward_lines(cfg["grid"], p[sample], th[sample], np.abs(img).astype(np.float64))
-    H.assert_within_bar(got[sample], ref, scl, what="config 3 sampled forward")
+    H.assert_within_bar(got[sample], ref, scl, what="cone_256 sampled forward")
     # constant image: every ray's integral is its chord through the box
     ones = plan.forward(torch.ones_like(dimg)).cpu().numpy().ravel()
     chords = np.array([ocore.chord_line(cfg["grid"], p[r], th[r]) for r in sample])

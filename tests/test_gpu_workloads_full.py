@@ -33,8 +33,8 @@ def _views_subset(scan, views):
     return sub
 
 
-def test_config4_full_sampled(xrt):
-    cfg = inputs.batched_config()
+def test_batched_cone_helical_full_sampled(xrt):
+    cfg = inputs.batched_workload()
     plans = [xrt.Plan(m["grid"], m["scan"]) for m in cfg["members"]]
     batch = xrt.Batch(plans)
     imgs_np = [inputs.random_image(inputs.image_shape(m["grid"]), m["seed"]) for m in cfg["members"]]
@@ -53,7 +53,7 @@ def test_config4_full_sampled(xrt):
         got = sinos[k].reshape(-1)[torch.from_numpy(global_idx).to(DEV)].cpu().numpy()
         ref = ocore.forward_lines(m["grid"], pl[pick], th[pick], imgs_np[k].astype(np.float64))
         scl = ocore.forward_lines(m["grid"], pl[pick], th[pick], np.abs(imgs_np[k]).astype(np.float64))
-        H.assert_within_bar(got, ref, scl, what=f"config 4 member {k} sampled forward")
+        H.assert_within_bar(got, ref, scl, what=f"batched member {k} sampled forward")
     # adjoint identity for every member: <A f, w> = <f, A^T w>
     gen = torch.Generator(device=DEV).manual_seed(7)
     ws = [torch.rand(tuple(p.sino_shape), generator=gen, device=DEV) for p in plans]
@@ -64,18 +64,18 @@ def test_config4_full_sampled(xrt):
         assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (k, lhs, rhs)
 
 
-def test_config5_full_parity(xrt):
-    cfg = inputs.config(5)
+def test_fan2d_256_sparse_full_parity(xrt):
+    cfg = inputs.workload("fan2d_256_sparse")
     grid, scan = cfg["grid"], cfg["scan"]
     plan = xrt.Plan(grid, scan)
     imgs = np.stack([inputs.ellipse_phantom(256, 256, 10, 5000 + k) for k in range(4)])
     got = plan.forward(torch.from_numpy(imgs).to(DEV)).cpu().numpy()
     for b in range(4):
         ref, scl = H.forward_bar(grid, scan, imgs[b])
-        H.assert_within_bar(got[b], ref, scl, what=f"config 5 forward {b}")
+        H.assert_within_bar(got[b], ref, scl, what=f"fan2d_256_sparse forward {b}")
     rng = np.random.default_rng(5)
     w = rng.normal(size=(4,) + tuple(plan.sino_shape)).astype(np.float32)
     back = plan.adjoint(torch.from_numpy(w).to(DEV)).cpu().numpy()
     for b in range(4):
         ref, scl = H.adjoint_bar(grid, scan, w[b])
-        H.assert_within_bar(back[b], ref, scl, what=f"config 5 adjoint {b}")
+        H.assert_within_bar(back[b], ref, scl, what=f"fan2d_256_sparse adjoint {b}")

@@ -137,9 +137,9 @@ def test_host_walk_worked_examples(walker, tmp_path, golden_dir):
         np.testing.assert_allclose(ln[o], gl, rtol=6e-6, atol=1e-6)
 
 
-def test_host_walk_config1_full(walker, tmp_path):
-    cfg = inputs.config(1)
+def test_host_walk_par2d_128_full(walker, tmp_path):
+    cfg = inputs.workload("par2d_128")
     rows = run_walk(walker, str(tmp_path), cfg["grid"], cfg["scan"])
     img = inputs.make_image(cfg)
     ref, scl = H.forward_bar(cfg["grid"], cfg["scan"], img)
-    H.assert_within_bar(dense_forward(rows, img), ref, scl, rtol=1e-9, what="config 1 host walk")
+    H.assert_within_bar(dense_forward(rows, img), ref, scl, rtol=1e-9, what="par2d_128 host walk")
