@@ -250,7 +250,7 @@ def main():
 
     value = M / (ms_step * 1e-3) / 1e6
     out = {
-        "metric": "Mrays/s fwd+adj at 256^3 cone",
+        "metric": "Mrays/s fwd+adj at 256\u00b3 cone (%HBM roofline); time-to-1e-3 learned vs CGLS",
         "value": round(value, 2),
         "unit": "Mrays/s",
         "n_gpus": 1,
