@@ -217,7 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
                 acc[q] = fma((double)g0, l0, acc[q]);
                 acc[q] = fma((double)g1, l1, acc[q]);
                 if constexpr (NR > 2) {
-                    // rarely needed: only where the shadow spans more than one bin
+                    // only where some lane's shadow spans more than one bin (whole waves
+                    // skip it often enough that evaluating it always is slower)
                     const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
                     if (vhi + kRangeSlack >= (double)(r0 + 2)) {
 #pragma unroll

@@ -2,9 +2,12 @@
 // scatter adjoint and per-ray hit lists.  The per-ray work (ray construction, clip, slab
 // walk with the paper's range condition and length formula) is in xrt_walk.h.
 //
-// One lane per ray; a wavefront holds 64 consecutive detector columns of one (view, row),
-// so neighbouring lanes walk neighbouring, nearly parallel rays through the same part of
-// the image.  Image and sinogram data are float32; line integrals accumulate in FP64.
+// One lane per ray; by default a wavefront holds 64 consecutive rays in (view, row,
+// column) order -- 64 neighbouring detector columns of one row -- so neighbouring lanes
+// walk neighbouring, nearly parallel rays through the same part of the image (a plan can
+// ask for packets of 32 x 2 or 16 x 4 detector cells instead, and an XCD-aware block
+// order).  A batch of plans runs as one persistent launch over a queue of ray chunks.
+// Image and sinogram data are float32; line integrals accumulate in FP64.
 #include "xrt_walk.h"
 
 namespace xrt {
