@@ -236,6 +236,39 @@ xrt_status xrt_batch_forward(xrt_batch* batch, const float* const* d_imgs, float
 xrt_status xrt_batch_adjoint(xrt_batch* batch, const float* const* d_sinos, float* const* d_imgs, int32_t mode,
                              void* stream);
 
+/* ---- the projection matrix in sparse storage ----
+ * The paper notes that the method can output the projection matrix in sparse storage: a
+ * row of A is the hit list of one ray (unit index, length), as xrt_ray_hits writes it for
+ * consecutive rays with row offsets from xrt_ray_hit_counts.  Stored, A and its transpose
+ * turn every product into one gather and one multiply-add per nonzero and image. */
+
+/* int64 elements of workspace xrt_offsets_from_counts needs for n counts (-1: n < 0). */
+int64_t xrt_scan_workspace(int64_t n);
+
+/* d_offsets[i] = d_counts[0] + ... + d_counts[i-1] for i = 0..n (int64 [n+1]); counts are
+ * int32 [n].  Deterministic.  d_work: int64 [xrt_scan_workspace(n)]. */
+xrt_status xrt_offsets_from_counts(int64_t n, const int32_t* d_counts, int64_t* d_offsets, int64_t* d_work,
+                                   void* stream);
+
+/* int64 elements of workspace xrt_csr_transpose needs (-1: n_cols < 0). */
+int64_t xrt_csr_transpose_workspace(int64_t n_cols);
+
+/* Transpose of a CSR matrix with n_rows rows, n_cols columns and nnz nonzeros (d_off int64
+ * [n_rows+1], d_col int32 [nnz] in [0, n_cols), d_val float [nnz]) into d_t_off int64
+ * [n_cols+1], d_t_col int32 [nnz], d_t_val float [nnz]; the entries of every transposed
+ * row are sorted by column, so the result is unique (deterministic).  Sizes up to 2^31-1
+ * rows and columns; d_work int64 [work_len >= xrt_csr_transpose_workspace(n_cols)]. */
+xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_off, const int32_t* d_col,
+                             const float* d_val, int64_t* d_t_off, int32_t* d_t_col, float* d_t_val, int64_t* d_work,
+                             int64_t work_len, void* stream);
+
+/* d_y[b][r] = sum over row r of val * d_x[b][col] for b < batch (d_x float [batch][n_cols],
+ * d_y float [batch][n_rows]); FP64 accumulation in the row's order (deterministic).  A
+ * column index outside [0, n_cols) reads 0.  batch * n_cols * 4 bytes must fit in 31 bits
+ * (XRT_E_ARG otherwise). */
+xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col, const float* d_val,
+                        int32_t batch, const float* d_x, float* d_y, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* xrt_status_str(int32_t status);
 

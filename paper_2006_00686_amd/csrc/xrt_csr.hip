@@ -1,0 +1,271 @@
+// The projection matrix in sparse storage: row offsets from per-row counts (exclusive
+// scan), a deterministic CSR transpose and a batched CSR product, on gfx950.
+//
+// A row of A is the hit list of one ray (unit indices and lengths, as xrt_ray_hits
+// writes them); its transpose holds, per unit, the rays that hit it.  With A stored, a
+// product costs one gather and one multiply-add per nonzero per image instead of the walk
+// of every ray, which pays for repeated products on small problems (iterative solves).
+#include <hip/hip_runtime.h>
+
+#include "xrt_internal.h"
+
+namespace xrt {
+namespace {
+
+constexpr int kSB = 256;            // threads of a scan block
+constexpr int kSPer = 4;            // elements per thread
+constexpr int kSChunk = kSB * kSPer;
+
+// exclusive scan of one block's kSChunk values (in registers) in LDS; returns the block total
+__device__ int64_t block_scan(int64_t (&v)[kSPer], int64_t* s)
+{
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) {
+        const int64_t t = v[i];
+        v[i] = sum;
+        sum += t;
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread sums
+    for (int d = 1; d < kSB; d <<= 1) {
+        const int64_t add = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int64_t before = threadIdx.x > 0 ? s[threadIdx.x - 1] : 0;
+    const int64_t total = s[kSB - 1];
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) v[i] += before;
+    __syncthreads();
+    return total;
+}
+
+// phase 1: total of every block of counts
+__global__ __launch_bounds__(kSB) void k_scan_sums(const int32_t* __restrict__ counts, int64_t n,
+                                                   int64_t* __restrict__ sums)
+{
+    __shared__ int64_t s[kSB];
+    const int64_t base = (int64_t)blockIdx.x * kSChunk + threadIdx.x * kSPer;
+    int64_t v[kSPer];
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) v[i] = base + i < n ? counts[base + i] : 0;
+    const int64_t total = block_scan(v, s);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// phase 2 (one block): exclusive scan of the block totals, in chunks
+__global__ __launch_bounds__(kSB) void k_scan_totals(int64_t* __restrict__ sums, int64_t nblocks)
+{
+    __shared__ int64_t s[kSB];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += kSChunk) {
+        const int64_t base = c0 + threadIdx.x * kSPer;
+        int64_t v[kSPer];
+#pragma unroll
+        for (int i = 0; i < kSPer; ++i) v[i] = base + i < nblocks ? sums[base + i] : 0;
+        const int64_t total = block_scan(v, s);
+#pragma unroll
+        for (int i = 0; i < kSPer; ++i)
+            if (base + i < nblocks) sums[base + i] = v[i] + carry;
+        carry += total;
+    }
+    if (threadIdx.x == 0) sums[nblocks] = carry;
+}
+
+// phase 3: offsets[i] = sum of counts[0 .. i), offsets[n] = total
+__global__ __launch_bounds__(kSB) void k_scan_apply(const int32_t* __restrict__ counts, int64_t n,
+                                                    const int64_t* __restrict__ sums, int64_t nblocks,
+                                                    int64_t* __restrict__ offsets)
+{
+    __shared__ int64_t s[kSB];
+    const int64_t base = (int64_t)blockIdx.x * kSChunk + threadIdx.x * kSPer;
+    int64_t v[kSPer];
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) v[i] = base + i < n ? counts[base + i] : 0;
+    block_scan(v, s);
+    const int64_t add = sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i)
+        if (base + i < n) offsets[base + i] = v[i] + add;
+    if (blockIdx.x == 0 && threadIdx.x == 0) offsets[n] = sums[nblocks];
+}
+
+__global__ __launch_bounds__(kSB) void k_zero_i32(int32_t* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kSB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSB) p[i] = 0;
+}
+
+// nonzeros per column (integer atomics: the totals do not depend on their order)
+__global__ __launch_bounds__(kSB) void k_csr_count_cols(const int32_t* __restrict__ col, int64_t nnz,
+                                                        int32_t* __restrict__ counts)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kSB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kSB)
+        atomicAdd(counts + col[e], 1);
+}
+
+// place every nonzero of row r into its column's segment (order within a segment is
+// fixed afterwards by k_csr_sort_cols)
+__global__ __launch_bounds__(kSB) void k_csr_fill(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                                  const float* __restrict__ val, int64_t n_rows,
+                                                  const int64_t* __restrict__ t_off, int32_t* __restrict__ cursor,
+                                                  int32_t* __restrict__ t_col, float* __restrict__ t_val)
+{
+    const int64_t r = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    if (r >= n_rows) return;
+    for (int64_t e = off[r]; e < off[r + 1]; ++e) {
+        const int32_t c = col[e];
+        const int64_t pos = t_off[c] + atomicAdd(cursor + c, 1);
+        t_col[pos] = (int32_t)r;
+        t_val[pos] = val[e];
+    }
+}
+
+// sort every column's segment by row (insertion sort; rows are distinct, so the result
+// is unique and the transpose deterministic)
+__global__ __launch_bounds__(kSB) void k_csr_sort_cols(const int64_t* __restrict__ t_off, int64_t n_cols,
+                                                       int32_t* __restrict__ t_col, float* __restrict__ t_val)
+{
+    const int64_t c = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    if (c >= n_cols) return;
+    const int64_t a = t_off[c], b = t_off[c + 1];
+    for (int64_t i = a + 1; i < b; ++i) {
+        const int32_t key = t_col[i];
+        const float v = t_val[i];
+        int64_t j = i - 1;
+        while (j >= a && t_col[j] > key) {
+            t_col[j + 1] = t_col[j];
+            t_val[j + 1] = t_val[j];
+            --j;
+        }
+        t_col[j + 1] = key;
+        t_val[j + 1] = v;
+    }
+}
+
+// y[b][r] = sum_e val[e] x[b][col[e]] over row r, FP64 accumulation in the row's order;
+// one lane per row, BB images per lane.  The gathers are bounds-checked buffer loads
+// (a column index outside the input reads 0).
+constexpr int kSpmvBB = 8;
+
+__global__ __launch_bounds__(kSB) void k_csr_spmv(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                                  const float* __restrict__ val, int64_t n_rows, int32_t n_cols,
+                                                  int32_t batch, const float* __restrict__ x, float* __restrict__ y)
+{
+    const int64_t r = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    if (r >= n_rows) return;
+    const int32_t b0 = blockIdx.y * kSpmvBB;
+    const uint64_t a = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)hi << 32) | lo), (short)0, __builtin_amdgcn_readfirstlane(batch * n_cols * 4), 0x00020000);
+    double acc[kSpmvBB];
+#pragma unroll
+    for (int q = 0; q < kSpmvBB; ++q) acc[q] = 0.0;
+    const int64_t e1 = off[r + 1];
+    for (int64_t e = off[r]; e < e1; ++e) {
+        const int32_t c = col[e];
+        const double v = (double)val[e];
+#pragma unroll
+        for (int q = 0; q < kSpmvBB; ++q) {
+            const int32_t b = b0 + q;
+            const int32_t o = (b < batch && c >= 0 && c < n_cols) ? (b * n_cols + c) * 4 : (int32_t)0xFFFFFFF0u;
+            acc[q] = fma((double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0)), v,
+                         acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kSpmvBB; ++q)
+        if (b0 + q < batch) y[(int64_t)(b0 + q) * n_rows + r] = (float)acc[q];
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + kSB - 1) / kSB); }
+unsigned grid_capped(int64_t n) { const int64_t g = (n + kSB - 1) / kSB; return (unsigned)(g < 65536 ? g : 65536); }
+
+xrt_status scan(int64_t n, const int32_t* counts, int64_t* offsets, int64_t* work, hipStream_t s)
+{
+    const int64_t nblocks = (n + kSChunk - 1) / kSChunk;
+    if (nblocks > 0) {
+        hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nblocks), dim3(kSB), 0, s, counts, n, work);
+    }
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kSB), 0, s, work, nblocks);
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kSB), 0, s, counts, n, work, nblocks, offsets);
+    else
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kSB), 0, s, counts, n, work, nblocks, offsets);
+    return hip_fail(hipGetLastError(), "scan launch");
+}
+
+}  // namespace
+}  // namespace xrt
+
+using namespace xrt;
+
+extern "C" {
+
+int64_t xrt_scan_workspace(int64_t n)
+{
+    return n < 0 ? -1 : (n + kSChunk - 1) / kSChunk + 1;
+}
+
+xrt_status xrt_offsets_from_counts(int64_t n, const int32_t* d_counts, int64_t* d_offsets, int64_t* d_work,
+                                   void* stream)
+{
+    if (n < 0 || n > ((int64_t)1 << 40) || (n > 0 && !d_counts) || !d_offsets || !d_work) {
+        set_error("xrt_offsets_from_counts: bad argument");
+        return XRT_E_ARG;
+    }
+    return scan(n, d_counts, d_offsets, d_work, (hipStream_t)stream);
+}
+
+int64_t xrt_csr_transpose_workspace(int64_t n_cols)
+{
+    return n_cols < 0 ? -1 : 2 * (n_cols + 1) + xrt_scan_workspace(n_cols) + 1;
+}
+
+xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_off, const int32_t* d_col,
+                             const float* d_val, int64_t* d_t_off, int32_t* d_t_col, float* d_t_val, int64_t* d_work,
+                             int64_t work_len, void* stream)
+{
+    if (n_rows < 0 || n_cols < 0 || n_cols > INT32_MAX || n_rows > INT32_MAX || nnz < 0 || !d_off || !d_t_off ||
+        !d_work || (nnz > 0 && (!d_col || !d_val || !d_t_col || !d_t_val)) ||
+        work_len < xrt_csr_transpose_workspace(n_cols)) {
+        set_error("xrt_csr_transpose: bad argument or workspace too small");
+        return XRT_E_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // workspace: counts / cursor (n_cols int32, in int64 slots) then the scan's block totals
+    int32_t* counts = (int32_t*)d_work;
+    int64_t* sw = d_work + (n_cols + 1);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_capped(n_cols + 1)), dim3(kSB), 0, s, counts, n_cols + 1);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_csr_count_cols, dim3(grid_capped(nnz)), dim3(kSB), 0, s, d_col, nnz, counts);
+    xrt_status st = scan(n_cols, counts, d_t_off, sw, s);
+    if (st != XRT_OK) return st;
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_capped(n_cols + 1)), dim3(kSB), 0, s, counts, n_cols + 1);
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_csr_fill, dim3(grid_of(n_rows)), dim3(kSB), 0, s, d_off, d_col, d_val, n_rows, d_t_off,
+                           counts, d_t_col, d_t_val);
+    if (n_cols > 0)
+        hipLaunchKernelGGL(k_csr_sort_cols, dim3(grid_of(n_cols)), dim3(kSB), 0, s, d_t_off, n_cols, d_t_col, d_t_val);
+    return hip_fail(hipGetLastError(), "xrt_csr_transpose launch");
+}
+
+xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col, const float* d_val,
+                        int32_t batch, const float* d_x, float* d_y, void* stream)
+{
+    if (n_rows < 0 || n_cols < 0 || batch < 1 || batch > 65535 * kSpmvBB || !d_off || !d_x || !d_y ||
+        (int64_t)batch * n_cols * 4 > INT32_MAX - 16) {
+        set_error("xrt_csr_spmv: bad argument or input too large for 32-bit offsets");
+        return XRT_E_ARG;
+    }
+    if (n_rows == 0) return XRT_OK;
+    const dim3 g(grid_of(n_rows), (unsigned)((batch + kSpmvBB - 1) / kSpmvBB));
+    hipLaunchKernelGGL(k_csr_spmv, g, dim3(kSB), 0, (hipStream_t)stream, d_off, d_col, d_val, n_rows, (int32_t)n_cols,
+                       batch, d_x, d_y);
+    return hip_fail(hipGetLastError(), "xrt_csr_spmv launch");
+}
+
+}  // extern "C"

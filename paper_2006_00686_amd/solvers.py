@@ -33,6 +33,22 @@ class PlanOperator:
         return self.plan.adjoint(y, mode=self.adjoint_mode, out=out)
 
 
+class MatrixOperator:
+    """A and A^T as products with the stored projection matrix (xrt.SparseMatrix)."""
+
+    def __init__(self, A):
+        self.A = A
+        self.At = A.transpose()
+        self.domain_shape = tuple(A.col_shape)
+        self.range_shape = tuple(A.row_shape)
+
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self.A.matmul(x, out=out)
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self.At.matmul(y, out=out)
+
+
 class RightPreconditioned:
     """A P with a linear preconditioner P (apply / adjoint on the image space)."""
 
@@ -123,7 +139,7 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
     return out, info
 
 
-def pcgls(op: PlanOperator, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
+def pcgls(op, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
           fallback: bool = True, stall_checks: int = 4):
     """Right-preconditioned CGLS: min ||A P z - g||, image f = P z.
 

@@ -82,6 +82,13 @@ def _lib():
         lib.xrt_batch_destroy.argtypes = [vp]
         lib.xrt_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         lib.xrt_batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        lib.xrt_scan_workspace.argtypes = [i64]
+        lib.xrt_scan_workspace.restype = i64
+        lib.xrt_offsets_from_counts.argtypes = [i64, vp, vp, vp, vp]
+        lib.xrt_csr_transpose_workspace.argtypes = [i64]
+        lib.xrt_csr_transpose_workspace.restype = i64
+        lib.xrt_csr_transpose.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+        lib.xrt_csr_spmv.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
                   "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
                   "xrt_vec_xpby_ratio", "xrt_vec_axpby", "xrt_conv3x3", "xrt_conv3x3_wgrad"):
@@ -242,8 +249,7 @@ class Plan:
         """(offsets[n+1], idx, len) CSR of rays [first, first+n), rows in traversal order."""
         counts = self.hit_counts(first, n, eps)
         n = counts.numel()
-        offs = torch.zeros(n + 1, dtype=torch.int64, device=counts.device)
-        offs[1:] = torch.cumsum(counts.to(torch.int64), 0)
+        offs = offsets_from_counts(counts)
         total = int(offs[-1].item())
         idx = torch.empty(max(total, 1), dtype=torch.int32, device=counts.device)
         ln = torch.empty(max(total, 1), dtype=torch.float32, device=counts.device)
@@ -397,3 +403,74 @@ def precond_apply(x: torch.Tensor, w1: torch.Tensor, w2: torch.Tensor, w3: torch
     _check(_lib().xrt_precond_apply(int(transposed), B, H, W, _ptr(x), _ptr(w1), _ptr(w2), _ptr(w3), _ptr(out),
                                     _stream(x.device.index)), "xrt_precond_apply")
     return out
+
+
+# ------------------------------------------------------------------ sparse storage of A
+
+
+def offsets_from_counts(counts: torch.Tensor) -> torch.Tensor:
+    """int64 [n+1] exclusive prefix sums of int32 counts [n] (deterministic)."""
+    n = counts.numel()
+    dev = counts.device
+    if counts.dtype != torch.int32 or not counts.is_contiguous():
+        raise ValueError("counts must be contiguous int32")
+    offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    work = torch.empty(int(_lib().xrt_scan_workspace(n)), dtype=torch.int64, device=dev)
+    _check(_lib().xrt_offsets_from_counts(n, _ptr(counts) if n else None, _ptr(offs), _ptr(work),
+                                          _stream(dev.index)), "xrt_offsets_from_counts")
+    return offs
+
+
+class SparseMatrix:
+    """A (and its transpose) in CSR storage on the device: rows are rays, columns units."""
+
+    def __init__(self, n_rows: int, n_cols: int, off: torch.Tensor, col: torch.Tensor, val: torch.Tensor,
+                 row_shape=None, col_shape=None):
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+        self.off, self.col, self.val = off, col, val
+        self.nnz = int(col.numel())
+        self.row_shape = tuple(row_shape) if row_shape is not None else (self.n_rows,)
+        self.col_shape = tuple(col_shape) if col_shape is not None else (self.n_cols,)
+        self._t = None
+
+    @classmethod
+    def from_plan(cls, plan: "Plan", eps: float = 0.0) -> "SparseMatrix":
+        """Hit lists of every ray of the plan (lengths > eps), as rows of A."""
+        off, idx, ln = plan.hits(0, None, eps)
+        return cls(plan.n_rays, plan.n_units, off, idx.contiguous(), ln.contiguous(), plan.sino_shape,
+                   plan.image_shape)
+
+    def transpose(self) -> "SparseMatrix":
+        if self._t is None:
+            dev = self.off.device
+            t_off = torch.empty(self.n_cols + 1, dtype=torch.int64, device=dev)
+            t_col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+            t_val = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=dev)
+            wl = int(_lib().xrt_csr_transpose_workspace(self.n_cols))
+            work = torch.empty(wl, dtype=torch.int64, device=dev)
+            _check(_lib().xrt_csr_transpose(self.n_rows, self.n_cols, self.nnz, _ptr(self.off),
+                                            _ptr(self.col) if self.nnz else None,
+                                            _ptr(self.val) if self.nnz else None, _ptr(t_off), _ptr(t_col),
+                                            _ptr(t_val), _ptr(work), wl, _stream(dev.index)), "xrt_csr_transpose")
+            t = SparseMatrix(self.n_cols, self.n_rows, t_off, t_col[:self.nnz], t_val[:self.nnz], self.col_shape,
+                             self.row_shape)
+            t._t = self
+            self._t = t
+        return self._t
+
+    def matmul(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y[b] = A x[b] for x [..., *col_shape] float32 contiguous."""
+        n = len(self.col_shape)
+        if tuple(x.shape[x.dim() - n:]) != self.col_shape or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError(f"expected contiguous float32 [..., {self.col_shape}], got {x.dtype} {tuple(x.shape)}")
+        lead = tuple(x.shape[:x.dim() - n])
+        b = int(np.prod(lead)) if lead else 1
+        if out is None:
+            out = torch.empty(lead + self.row_shape, dtype=torch.float32, device=x.device)
+        _check(_lib().xrt_csr_spmv(self.n_rows, self.n_cols, _ptr(self.off), _ptr(self.col) if self.nnz else None,
+                                   _ptr(self.val) if self.nnz else None, b, _ptr(x), _ptr(out),
+                                   _stream(x.device.index)), "xrt_csr_spmv")
+        return out
+
+    def bytes(self) -> int:
+        return self.off.numel() * 8 + self.nnz * 8

@@ -1,0 +1,103 @@
+"""GPU: the projection matrix in sparse storage -- prefix sums, A as CSR built from the
+hit lists of every ray, its deterministic transpose, and products with both against the
+oracle and the on-the-fly transform; CGLS with the stored matrix."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import tests.helpers as H
+from paper_2006_00686_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+KINDS = ["par2d", "fan2d_flat", "fan2d_arc", "par3d", "cone_flat", "helical", "cone_arc"]
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_00686_amd import xrt
+    xrt.library()
+    return xrt
+
+
+@pytest.mark.parametrize("n", [0, 1, 1023, 1024, 1025, 5000, 300001])
+def test_offsets_from_counts(X, n):
+    rng = np.random.default_rng(n)
+    c = rng.integers(0, 700, size=n).astype(np.int32)
+    got = X.offsets_from_counts(torch.from_numpy(c).to(DEV)).cpu().numpy()
+    ref = np.concatenate([[0], np.cumsum(c.astype(np.int64))])
+    np.testing.assert_array_equal(got, ref)
+
+
+def _scan(name):
+    return {n: (g, s) for n, g, s in H.small_scans()}[name]
+
+
+@pytest.mark.parametrize("name", KINDS)
+def test_stored_matrix_products(X, name):
+    grid, scan = _scan(name)
+    plan = X.Plan(grid, scan)
+    A = X.SparseMatrix.from_plan(plan)
+    At = A.transpose()
+    rng = np.random.default_rng(3)
+    img = rng.uniform(0, 1, size=(2,) + tuple(plan.image_shape)).astype(np.float32)
+    w = rng.normal(size=(2,) + tuple(plan.sino_shape)).astype(np.float32)
+    fwd = A.matmul(torch.from_numpy(img).to(DEV)).cpu().numpy()
+    adj = At.matmul(torch.from_numpy(w).to(DEV)).cpu().numpy()
+    for b in range(2):
+        ref, scl = H.forward_bar(grid, scan, img[b])
+        H.assert_within_bar(fwd[b], ref, scl, what=f"stored A {name}")
+        ref, scl = H.adjoint_bar(grid, scan, w[b])
+        H.assert_within_bar(adj[b], ref, scl, what=f"stored A^T {name}")
+    # the on-the-fly transform gives the same values (lengths stored in FP32)
+    otf = plan.forward(torch.from_numpy(img).to(DEV)).cpu().numpy()
+    ref, scl = H.forward_bar(grid, scan, img[0])
+    H.assert_within_bar(fwd[0], otf[0], scl, rtol=1e-6, what=f"stored vs on-the-fly {name}")
+
+
+def test_transpose_is_exact_and_deterministic(X):
+    grid, scan = _scan("cone_flat")
+    plan = X.Plan(grid, scan)
+    A = X.SparseMatrix.from_plan(plan)
+    off, col, val = (t.cpu().numpy() for t in (A.off, A.col, A.val))
+    rows = np.repeat(np.arange(A.n_rows), np.diff(off))
+    order = np.lexsort((rows, col))                      # by column, then row
+    ref_off = np.concatenate([[0], np.cumsum(np.bincount(col, minlength=A.n_cols))])
+    T = A.transpose()
+    np.testing.assert_array_equal(T.off.cpu().numpy(), ref_off)
+    np.testing.assert_array_equal(T.col.cpu().numpy(), rows[order])
+    np.testing.assert_array_equal(T.val.cpu().numpy(), val[order])
+    T2 = X.SparseMatrix(A.n_rows, A.n_cols, A.off, A.col, A.val).transpose()
+    np.testing.assert_array_equal(T2.col.cpu().numpy(), T.col.cpu().numpy())
+    # and back: the transpose of the transpose lists every row's hits sorted by unit
+    TT = X.SparseMatrix(T.n_rows, T.n_cols, T.off, T.col, T.val).transpose()
+    np.testing.assert_array_equal(TT.off.cpu().numpy(), off)
+    order_rows = np.lexsort((col, rows))
+    np.testing.assert_array_equal(TT.col.cpu().numpy(), col[order_rows])
+
+
+def test_cgls_with_stored_matrix(X):
+    from paper_2006_00686_amd import learned, solvers
+    cfg = inputs.workload("fan2d_256_sparse")
+    plan = X.Plan(cfg["grid"], cfg["scan"])
+    g = learned.training_batch(cfg, plan, 8, learned.EVAL_SEED0, DEV)
+    A = X.SparseMatrix.from_plan(plan)
+    xm, im = solvers.cgls(solvers.MatrixOperator(A), g, 300, tol=1e-3, check_every=1)
+    xp, ip = solvers.cgls(solvers.PlanOperator(plan), g, 300, tol=1e-3, check_every=1)
+    assert im.converged and ip.converged
+    assert abs(im.iterations - ip.iterations) <= 2, (im.iterations, ip.iterations)
+    k = min(len(im.rel_residual), len(ip.rel_residual))
+    np.testing.assert_allclose(im.rel_residual[:k], ip.rel_residual[:k], rtol=2e-2)
+
+
+def test_spmv_rejects_oversized_input(X):
+    grid, scan = _scan("par2d")
+    plan = X.Plan(grid, scan)
+    A = X.SparseMatrix.from_plan(plan)
+    # 4 images of 600M columns exceed the 31-bit byte offsets: rejected before any launch
+    st = X._lib().xrt_csr_spmv(A.n_rows, 600_000_000, X._ptr(A.off), X._ptr(A.col), X._ptr(A.val), 4,
+                               X._ptr(A.val), X._ptr(A.val), None)
+    assert st == -1
