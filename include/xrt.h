@@ -269,6 +269,19 @@ xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const 
 xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col, const float* d_val,
                         int32_t batch, const float* d_x, float* d_y, void* stream);
 
+/* [batch][n] -> [n][batch] (to_interleaved != 0) or back, batch in [1, 64]; d_in and
+ * d_out must be distinct. */
+xrt_status xrt_interleave(int64_t n, int32_t batch, int32_t to_interleaved, const float* d_in, float* d_out,
+                          void* stream);
+
+/* xrt_csr_spmv on batch-interleaved vectors: d_y_il[r][b] = sum over row r of
+ * val * d_x_il[col][b] (d_x_il float [n_cols][batch], d_y_il float [n_rows][batch], batch in
+ * [1, 64]); one wavefront per row with the images in its lanes, so each nonzero reads the
+ * batch's values of one unit from contiguous memory.  Same arithmetic and order as
+ * xrt_csr_spmv. */
+xrt_status xrt_csr_spmv_interleaved(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col,
+                                   const float* d_val, int32_t batch, const float* d_x_il, float* d_y_il, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* xrt_status_str(int32_t status);
 

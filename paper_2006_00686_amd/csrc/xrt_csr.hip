@@ -181,6 +181,67 @@ __global__ __launch_bounds__(kSB) void k_csr_spmv(const int64_t* __restrict__ of
         if (b0 + q < batch) y[(int64_t)(b0 + q) * n_rows + r] = (float)acc[q];
 }
 
+// Batch-interleaved product: x_il [n_cols][batch], y_il [n_rows][batch] (batch <= 64).
+// One wavefront per row, lane = image: the row's indices and values are wave-uniform
+// (scalar loads) and each nonzero gathers the batch's 64 values of one unit from 256
+// contiguous bytes.  FP64 accumulation in the row's order.
+constexpr int kIlRows = kSB / 64;
+
+__global__ __launch_bounds__(kSB) void k_csr_spmv_il(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ val, int64_t n_rows, int32_t n_cols,
+                                                     int32_t batch, const float* __restrict__ x_il,
+                                                     float* __restrict__ y_il)
+{
+    const int32_t lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * kIlRows + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (r >= n_rows) return;
+    const uint64_t a = (uint64_t)x_il;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)hi << 32) | lo), (short)0, __builtin_amdgcn_readfirstlane(batch * n_cols * 4), 0x00020000);
+    const int32_t lane_off = lane < batch ? lane * 4 : (int32_t)0xFFFFFFF0u;
+    double acc = 0.0;
+    const int64_t e0 = off[r], e1 = off[r + 1];
+    // 64 nonzeros at a time: one coalesced load of their indices and values, then each is
+    // broadcast from its lane in turn (the gathers of consecutive nonzeros are independent)
+    for (int64_t base = e0; base < e1; base += 64) {
+        const int64_t e = base + lane;
+        const int32_t cl = e < e1 ? col[e] : -1;
+        const int32_t vl = e < e1 ? __builtin_bit_cast(int32_t, val[e]) : 0;
+        const int32_t cnt = (int32_t)(e1 - base < 64 ? e1 - base : 64);
+#pragma unroll 8
+        for (int32_t j = 0; j < cnt; ++j) {
+            const int32_t c = __builtin_amdgcn_readlane(cl, j);
+            const double v = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(vl, j));
+            const int32_t o = (c >= 0 && c < n_cols) ? c * batch * 4 + lane_off : (int32_t)0xFFFFFFF0u;
+            acc = fma((double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0)), v, acc);
+        }
+    }
+    if (lane < batch) y_il[r * batch + lane] = (float)acc;
+}
+
+// [batch][n] <-> [n][batch] through an LDS tile of 64 elements x up to 64 images
+__global__ __launch_bounds__(kSB) void k_interleave(const float* __restrict__ in, float* __restrict__ out, int64_t n,
+                                                    int32_t batch, int32_t to_il)
+{
+    __shared__ float tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (to_il) {
+        for (int32_t b = ty; b < batch; b += kSB / 64)
+            if (i0 + tx < n) tile[b][tx] = in[(int64_t)b * n + i0 + tx];
+        __syncthreads();
+        for (int32_t k = ty; k < 64; k += kSB / 64)
+            if (i0 + k < n && tx < batch) out[(i0 + k) * batch + tx] = tile[tx][k];
+    } else {
+        for (int32_t k = ty; k < 64; k += kSB / 64)
+            if (i0 + k < n && tx < batch) tile[tx][k] = in[(i0 + k) * batch + tx];
+        __syncthreads();
+        for (int32_t b = ty; b < batch; b += kSB / 64)
+            if (i0 + tx < n) out[(int64_t)b * n + i0 + tx] = tile[b][tx];
+    }
+}
+
 unsigned grid_of(int64_t n) { return (unsigned)((n + kSB - 1) / kSB); }
 unsigned grid_capped(int64_t n) { const int64_t g = (n + kSB - 1) / kSB; return (unsigned)(g < 65536 ? g : 65536); }
 
@@ -266,6 +327,33 @@ xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, co
     hipLaunchKernelGGL(k_csr_spmv, g, dim3(kSB), 0, (hipStream_t)stream, d_off, d_col, d_val, n_rows, (int32_t)n_cols,
                        batch, d_x, d_y);
     return hip_fail(hipGetLastError(), "xrt_csr_spmv launch");
+}
+
+xrt_status xrt_interleave(int64_t n, int32_t batch, int32_t to_interleaved, const float* d_in, float* d_out,
+                          void* stream)
+{
+    if (n < 0 || batch < 1 || batch > 64 || !d_in || !d_out || d_in == d_out) {
+        set_error("xrt_interleave: bad argument (batch in [1, 64], distinct buffers)");
+        return XRT_E_ARG;
+    }
+    if (n == 0) return XRT_OK;
+    hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 63) / 64)), dim3(kSB), 0, (hipStream_t)stream, d_in, d_out, n,
+                       batch, to_interleaved ? 1 : 0);
+    return hip_fail(hipGetLastError(), "xrt_interleave launch");
+}
+
+xrt_status xrt_csr_spmv_interleaved(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col,
+                                   const float* d_val, int32_t batch, const float* d_x_il, float* d_y_il, void* stream)
+{
+    if (n_rows < 0 || n_cols < 0 || batch < 1 || batch > 64 || !d_off || !d_x_il || !d_y_il ||
+        (int64_t)batch * n_cols * 4 > INT32_MAX - 16 || (n_rows + kIlRows - 1) / kIlRows > INT32_MAX) {
+        set_error("xrt_csr_spmv_interleaved: bad argument (batch in [1, 64]) or input too large");
+        return XRT_E_ARG;
+    }
+    if (n_rows == 0) return XRT_OK;
+    hipLaunchKernelGGL(k_csr_spmv_il, dim3((unsigned)((n_rows + kIlRows - 1) / kIlRows)), dim3(kSB), 0,
+                       (hipStream_t)stream, d_off, d_col, d_val, n_rows, (int32_t)n_cols, batch, d_x_il, d_y_il);
+    return hip_fail(hipGetLastError(), "xrt_csr_spmv_interleaved launch");
 }
 
 }  // extern "C"

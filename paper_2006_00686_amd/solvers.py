@@ -12,6 +12,7 @@ import math
 import time
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 from . import xrt as X
@@ -34,19 +35,41 @@ class PlanOperator:
 
 
 class MatrixOperator:
-    """A and A^T as products with the stored projection matrix (xrt.SparseMatrix)."""
+    """A and A^T as products with the stored projection matrix (xrt.SparseMatrix).
+
+    Batches of 2..64 problems run interleaved ([unit][problem]: each nonzero reads the
+    batch's values from contiguous memory) through buffers kept between calls."""
 
     def __init__(self, A):
         self.A = A
         self.At = A.transpose()
         self.domain_shape = tuple(A.col_shape)
         self.range_shape = tuple(A.row_shape)
+        self._bufs = {}
+
+    def _il(self, batch, dev):
+        if batch not in self._bufs:
+            self._bufs[batch] = (torch.empty((self.A.n_cols, batch), dtype=torch.float32, device=dev),
+                                 torch.empty((self.A.n_rows, batch), dtype=torch.float32, device=dev))
+        return self._bufs[batch]
+
+    def _product(self, M, x, out, in_shape, out_shape):
+        batch = x.numel() // int(np.prod(in_shape))
+        if out is None:
+            out = torch.empty((batch,) + tuple(out_shape), dtype=torch.float32, device=x.device)
+        if batch < 2 or batch > 64:
+            return M.matmul(x, out=out)
+        bi, bo = self._il(batch, x.device)
+        xi, yo = (bi, bo) if M is self.A else (bo, bi)
+        X.interleave(x, batch, out=xi)
+        M.matmul_interleaved(xi, batch, out=yo)
+        return X.deinterleave(yo, batch, out)
 
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self.A.matmul(x, out=out)
+        return self._product(self.A, x, out, self.domain_shape, self.range_shape)
 
     def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self.At.matmul(y, out=out)
+        return self._product(self.At, y, out, self.range_shape, self.domain_shape)
 
 
 class RightPreconditioned:

@@ -89,6 +89,8 @@ def _lib():
         lib.xrt_csr_transpose_workspace.restype = i64
         lib.xrt_csr_transpose.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, i64, vp]
         lib.xrt_csr_spmv.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp]
+        lib.xrt_interleave.argtypes = [i64, i32, i32, vp, vp, vp]
+        lib.xrt_csr_spmv_interleaved.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp]
         for f in ("xrt_plan_create", "xrt_plan_destroy", "xrt_plan_sizes", "xrt_forward", "xrt_adjoint",
                   "xrt_ray_hit_counts", "xrt_ray_hits", "xrt_vec_dot", "xrt_vec_axpy_ratio",
                   "xrt_vec_xpby_ratio", "xrt_vec_axpby", "xrt_conv3x3", "xrt_conv3x3_wgrad"):
@@ -472,5 +474,33 @@ class SparseMatrix:
                                    _stream(x.device.index)), "xrt_csr_spmv")
         return out
 
+    def matmul_interleaved(self, x_il: torch.Tensor, batch: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """y_il [n_rows][batch] = A applied to x_il [n_cols][batch] (batch <= 64)."""
+        if x_il.dtype != torch.float32 or not x_il.is_contiguous() or x_il.numel() != self.n_cols * batch:
+            raise ValueError("x_il must be contiguous float32 [n_cols][batch]")
+        if out is None:
+            out = torch.empty((self.n_rows, batch), dtype=torch.float32, device=x_il.device)
+        _check(_lib().xrt_csr_spmv_interleaved(self.n_rows, self.n_cols, _ptr(self.off),
+                                               _ptr(self.col) if self.nnz else None,
+                                               _ptr(self.val) if self.nnz else None, batch, _ptr(x_il), _ptr(out),
+                                               _stream(x_il.device.index)), "xrt_csr_spmv_interleaved")
+        return out
+
     def bytes(self) -> int:
         return self.off.numel() * 8 + self.nnz * 8
+
+
+def interleave(x: torch.Tensor, batch: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """[batch][n] -> [n][batch] (batch <= 64)."""
+    n = x.numel() // batch
+    if out is None:
+        out = torch.empty((n, batch), dtype=torch.float32, device=x.device)
+    _check(_lib().xrt_interleave(n, batch, 1, _ptr(x), _ptr(out), _stream(x.device.index)), "xrt_interleave")
+    return out
+
+
+def deinterleave(x_il: torch.Tensor, batch: int, out: torch.Tensor) -> torch.Tensor:
+    """[n][batch] -> out [batch][...] (out preallocated with batch * n elements)."""
+    n = x_il.numel() // batch
+    _check(_lib().xrt_interleave(n, batch, 0, _ptr(x_il), _ptr(out), _stream(x_il.device.index)), "xrt_interleave")
+    return out

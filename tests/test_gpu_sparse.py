@@ -101,3 +101,23 @@ def test_spmv_rejects_oversized_input(X):
     st = X._lib().xrt_csr_spmv(A.n_rows, 600_000_000, X._ptr(A.off), X._ptr(A.col), X._ptr(A.val), 4,
                                X._ptr(A.val), X._ptr(A.val), None)
     assert st == -1
+
+
+@pytest.mark.parametrize("batch", [1, 5, 64])
+def test_interleaved_product_matches(X, batch):
+    grid, scan = _scan("fan2d_flat")
+    plan = X.Plan(grid, scan)
+    A = X.SparseMatrix.from_plan(plan)
+    rng = np.random.default_rng(batch)
+    x = torch.from_numpy(rng.normal(size=(batch,) + tuple(plan.image_shape)).astype(np.float32)).to(DEV)
+    ref = A.matmul(x)
+    xi = X.interleave(x, batch)
+    np.testing.assert_array_equal(xi.cpu().numpy(), x.reshape(batch, -1).T.cpu().numpy())
+    y = X.deinterleave(A.matmul_interleaved(xi, batch), batch, torch.empty_like(ref))
+    # same products in the same order: identical bits
+    np.testing.assert_array_equal(y.cpu().numpy(), ref.cpu().numpy())
+    At = A.transpose()
+    w = torch.from_numpy(rng.normal(size=(batch,) + tuple(plan.sino_shape)).astype(np.float32)).to(DEV)
+    from paper_2006_00686_amd import solvers
+    op = solvers.MatrixOperator(A)
+    np.testing.assert_array_equal(op.adjoint(w).cpu().numpy(), At.matmul(w).cpu().numpy())
