@@ -89,12 +89,27 @@ def learned_solve(torch, dev, tol: float = 1e-3):
         d = (plan.forward(x) - g).double().flatten(1)
         return float(torch.sqrt((d * d).sum(1) / (g.double().flatten(1) ** 2).sum(1)).max())
 
+    # the same solves with the projection matrix stored (CSR of A and its transpose)
+    from paper_2006_00686_amd import solvers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = xrt.SparseMatrix.from_plan(plan)
+    mop = solvers.MatrixOperator(A)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    rs = learned.evaluate(plan, P, g, tol=tol, op=mop)
+    rs.pop("images")
+    stored = {"build_s": round(build_s, 5), "nnz": A.nnz, "bytes": 2 * A.bytes(),
+              "cgls_s": round(rs["cgls"]["seconds"], 5), "cgls_iterations": rs["cgls"]["iterations"],
+              "pcgls_s": round(rs["pcgls"]["seconds"], 5), "pcgls_iterations": rs["pcgls"]["iterations"],
+              "speedup": round(rs["speedup"], 3)}
+
     return {"workload": cfg["name"], "batch": cfg["batch"], "tol": tol,
             "cgls_s": round(r["cgls"]["seconds"], 5), "cgls_iterations": r["cgls"]["iterations"],
             "pcgls_s": round(r["pcgls"]["seconds"], 5), "pcgls_iterations": r["pcgls"]["iterations"],
             "speedup": round(r["speedup"], 3), "fallback": r["pcgls"]["fallback"],
             "true_residual": {"cgls": true_residual(xc), "pcgls": true_residual(xp)},
-            "weights": os.path.relpath(learned.default_weights(), ROOT)}
+            "weights": os.path.relpath(learned.default_weights(), ROOT), "stored_matrix": stored}
 
 
 def batched_bench(torch, dev, steps: int, tuning: dict):

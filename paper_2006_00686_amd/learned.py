@@ -210,12 +210,13 @@ def default_weights() -> str:
 
 
 def evaluate(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, tol: float = 1e-3, max_iters: int = 3000,
-             check_every: int = 1) -> dict:
+             check_every: int = 1, op=None) -> dict:
     """Wall time from data on the device to the first iterate whose recursive residual
     satisfies ||r|| <= tol ||g|| for every problem of the batch: plain CGLS and CGLS
-    right-preconditioned by P.  Both solvers run once untimed first (kernel loading)."""
+    right-preconditioned by P, with the on-the-fly transform of the plan or the operator
+    `op` (e.g. the stored matrix).  Both solvers run once untimed first (kernel loading)."""
     from . import solvers
-    op = solvers.PlanOperator(plan)
+    op = op if op is not None else solvers.PlanOperator(plan)
     solvers.cgls(op, g, 2, tol, check_every)
     solvers.pcgls(op, P, g, 2, tol, check_every, fallback=False)
     xc, ic = solvers.cgls(op, g, max_iters, tol, check_every)
