@@ -28,6 +28,13 @@ def _axis_bounds(n, d, c, sign):
 
 def unit_lengths(g: dict, p, th):
     """Dense array (image shape) of len(ray, unit) for every unit."""
+    L, U = unit_intervals(g, p, th)
+    return np.maximum(U - L, 0.0)
+
+
+def unit_intervals(g: dict, p, th):
+    """Dense arrays (image shape) of the parameters t where the line p + t th enters and
+    leaves every unit (U <= L: not crossed)."""
     p = np.asarray(p, dtype=np.float64).ravel()
     th = np.asarray(th, dtype=np.float64).ravel()
     nz = int(g.get("nz", 0))
@@ -61,8 +68,9 @@ def unit_lengths(g: dict, p, th):
         L = np.maximum(tlo[1][:, None], tlo[0][None, :])
         U = np.minimum(thi[1][:, None], thi[0][None, :])
         M = member[1][:, None] & member[0][None, :]
-    ln = np.where(M, np.maximum(U - L, 0.0), 0.0)
-    return ln
+    L = np.where(M, L, 0.0)
+    U = np.where(M, U, 0.0)
+    return L, U
 
 
 def hits(g: dict, p, th, eps=0.0):

@@ -50,6 +50,8 @@ def _load():
         lib.ora_ray_hits.argtypes = [gp, dp, dp, lp, dp, ctypes.c_long, ctypes.c_double]
         lib.ora_ray_hits.restype = ctypes.c_long
         lib.ora_hit_counts.argtypes = [gp, ctypes.c_long, dp, dp, ctypes.c_double, lp, ctypes.c_int]
+        lib.ora_forward_att.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, dp, ctypes.c_int]
+        lib.ora_adjoint_att.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.ora_chord.argtypes = [gp, dp, dp]
         lib.ora_chord.restype = ctypes.c_double
         _lib = lib
@@ -102,6 +104,29 @@ def adjoint_lines(g: dict, p, th, sino, nthreads=None):
     return img.reshape(image_shape(g))
 
 
+def forward_att_lines(g: dict, p, th, img, mu, nthreads=None):
+    """Attenuated transform (Introduction, eq. generalizedRadontransform, SPECT case)."""
+    lib = _load()
+    p, th = _c(p).reshape(-1, 3), _c(th).reshape(-1, 3)
+    img, mu = _c(img), _c(mu)
+    out = np.zeros(p.shape[0], dtype=np.float64)
+    gg = _grid(g)
+    lib.ora_forward_att(ctypes.byref(gg), p.shape[0], _dptr(p), _dptr(th), _dptr(img), _dptr(mu), _dptr(out),
+                        nthreads or default_threads())
+    return out
+
+
+def adjoint_att_lines(g: dict, p, th, sino, mu, nthreads=None):
+    lib = _load()
+    p, th = _c(p).reshape(-1, 3), _c(th).reshape(-1, 3)
+    sino, mu = _c(sino).ravel(), _c(mu)
+    img = np.zeros(int(np.prod(image_shape(g))), dtype=np.float64)
+    gg = _grid(g)
+    lib.ora_adjoint_att(ctypes.byref(gg), p.shape[0], _dptr(p), _dptr(th), _dptr(sino), _dptr(mu), _dptr(img),
+                        nthreads or default_threads())
+    return img.reshape(image_shape(g))
+
+
 def ray_hits_line(g: dict, p, th, eps=0.0):
     """(indices, lengths) of one ray, sorted by 1D index; lengths > eps."""
     lib = _load()
@@ -140,6 +165,16 @@ def forward(g: dict, scan: dict, img, nthreads=None):
     """Sinogram of img for the scan (FP64), shaped like the scan's sinogram."""
     p, th = geometry.expand(scan)
     return forward_lines(g, p, th, img, nthreads).reshape(geometry.sino_shape(scan))
+
+
+def forward_att(g: dict, scan: dict, img, mu, nthreads=None):
+    p, th = geometry.expand(scan)
+    return forward_att_lines(g, p, th, img, mu, nthreads).reshape(geometry.sino_shape(scan))
+
+
+def adjoint_att(g: dict, scan: dict, sino, mu, nthreads=None):
+    p, th = geometry.expand(scan)
+    return adjoint_att_lines(g, p, th, sino, mu, nthreads)
 
 
 def adjoint(g: dict, scan: dict, sino, nthreads=None):

@@ -61,6 +61,17 @@ void ora_hit_counts(const ora_grid* g, long nrays, const double* p, const double
 /* Chord length of the line through the (half-open) image box. */
 double ora_chord(const ora_grid* g, const double* p, const double* th);
 
+/* Attenuated transform (Introduction, eq. generalizedRadontransform, SPECT case): the
+ * weight of a point is exp(-integral of mu from it to the detector side, +th); mu is a
+ * unit-wise constant attenuation map (1/length) on the same grid.
+ *   out[r] = sum over the chord's pieces i of img_i exp(-A_i) (1 - exp(-mu_i len_i)) / mu_i,
+ *   A_i = sum of mu_j len_j over the pieces after i (toward +th).
+ * ora_adjoint_att is its transpose (fixed-order reduction). */
+void ora_forward_att(const ora_grid* g, long nrays, const double* p, const double* th,
+                     const double* img, const double* mu, double* out, int nthreads);
+void ora_adjoint_att(const ora_grid* g, long nrays, const double* p, const double* th,
+                     const double* sino, const double* mu, double* img, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
