@@ -203,6 +203,19 @@ xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t h
                              const void* d_in, const void* d_dout, float* d_work, int64_t work_floats,
                              float* d_dweight, void* stream);
 
+/* Attenuated transform (Introduction, eq. generalizedRadontransform, SPECT case): each
+ * point of a ray is weighted by exp(-integral of mu from the point to the detector side
+ * of the ray; for divergent beams the side away from the source, for parallel beams the
+ * +theta side).  d_mu: attenuation per unit length, float32 with the image layout, one map
+ * for all images (mu_per_image = 0) or one per image.  Every hit piece of length len
+ * contributes f exp(-A) (1 - exp(-mu len)) / mu (f len where mu = 0), A the attenuation
+ * between the piece and the detector.  The adjoint is the exact transpose (ray-driven,
+ * atomics: summation order not fixed).  Same layouts and errors as xrt_forward. */
+xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const float* d_mu, int32_t mu_per_image,
+                                  float* d_sino, int32_t batch, void* stream);
+xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,
+                                  float* d_img, int32_t batch, void* stream);
+
 /* ---- launch shape of the forward projection (tuning; results do not depend on it) ----
  * packet_cols = 0: a wavefront takes 64 consecutive rays in (view, row, column) order;
  * 64, 32 or 16: a wavefront takes a packet of packet_cols detector columns x

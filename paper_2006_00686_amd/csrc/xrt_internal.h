@@ -132,6 +132,10 @@ xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const Dev
                                 const int32_t* order, const float* const* imgs, float* const* sinos,
                                 unsigned long long* counter, uint32_t grid, hipStream_t s);
 xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, hipStream_t s);
+xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride, float* sino,
+                              int batch, hipStream_t s);
+xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float* mu, int64_t mu_stride, float* img,
+                              int batch, hipStream_t s);
 uint32_t forward_batch_blocks_per_cu();
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
                                   hipStream_t s);

@@ -527,6 +527,26 @@ xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_
     return launch_forward(plan, d_img, d_sino, batch, (hipStream_t)stream);
 }
 
+xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const float* d_mu, int32_t mu_per_image,
+                                  float* d_sino, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_mu || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_forward_att(plan, d_img, d_mu, mu_per_image ? plan->dp.n_units : 0, d_sino, batch,
+                              (hipStream_t)stream);
+}
+
+xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,
+                                  float* d_img, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_mu || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_adjoint_att(plan, d_sino, d_mu, mu_per_image ? plan->dp.n_units : 0, d_img, batch,
+                              (hipStream_t)stream);
+}
+
 xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
                        void* stream)
 {

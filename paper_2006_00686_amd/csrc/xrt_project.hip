@@ -149,6 +149,77 @@ struct EmitVisit {
     }
 };
 
+// Attenuated transform (the generalised transform of the paper's Introduction with the
+// SPECT weight exp(-integral of mu from the point to the detector side of the ray)).  The
+// walk runs from the detector side back (the ray's direction reversed), so for every piece
+// the attenuation between it and the detector is the running sum A of mu * length over
+// the pieces already visited; a piece of length len with values f, mu contributes
+// f exp(-A) (1 - exp(-mu len)) / mu  (f len when mu = 0), its exact integral.
+__device__ __forceinline__ double att_weight(double m, double lp, double& em1)
+{
+    const double x = m * lp;
+    em1 = expm1(-x);
+    return x != 0.0 ? -em1 / m : lp;
+}
+
+struct AttFwdVisit {
+    static constexpr int32_t kIndexScale = 4;
+    __amdgpu_buffer_rsrc_t rf, rm;   // image and attenuation map
+    double scale;                     // physical length per unit of ray parameter
+    double E;                         // exp(-A)
+    double acc;
+    __device__ __forceinline__ void one(int32_t off, double l)
+    {
+        // a candidate that is not hit reads f = mu = 0 (out of range): it adds nothing
+        const double f = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, off, 0, 0));
+        const double m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, off, 0, 0));
+        double em1;
+        const double w = att_weight(m, l * scale, em1);
+        acc = fma(f * E, w, acc);
+        E *= 1.0 + em1;
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        one(I1, l1);
+        one(l2 > 0.0 ? I2 : kOutOfRange, l2);
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        one(I1, l1);
+        one(l2 > 0.0 ? I2 : kOutOfRange, l2);
+        one(l3 > 0.0 ? I3 : kOutOfRange, l3);
+    }
+};
+
+struct AttAdjVisit {
+    static constexpr int32_t kIndexScale = 1;
+    float* img;
+    __amdgpu_buffer_rsrc_t rm;
+    double scale, g, E;
+    __device__ __forceinline__ void one(int32_t I, double l)
+    {
+        if (!(l > 0.0)) return;
+        const double m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, I * 4, 0, 0));
+        double em1;
+        const double w = att_weight(m, l * scale, em1);
+        unsafeAtomicAdd(img + I, (float)(g * E * w));
+        E *= 1.0 + em1;
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        one(I1, l1);
+        one(I2, l2);
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        one(I1, l1);
+        one(I2, l2);
+        one(I3, l3);
+    }
+};
+
 // Ray of thread t when a wavefront covers a packet of P.packet_cols detector columns x
 // (64 / packet_cols) rows of one view, or -1 past the detector's edge.
 __device__ __forceinline__ int32_t packet_ray(const DevPlan& P, uint64_t t)
@@ -275,6 +346,43 @@ __global__ __launch_bounds__(kBlock) void k_forward_batch(const DevPlan* __restr
     }
 }
 
+// mu_stride: 0 (one attenuation map for every image) or the image size
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward_att(DevPlan P, const float* __restrict__ img,
+                                                         const float* __restrict__ mu, int64_t mu_stride,
+                                                         float* __restrict__ sino)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.n_rays) return;
+    const int64_t b = blockIdx.y;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];   // from the detector side back
+    const int32_t nb = (int32_t)(P.n_units * 4);
+    AttFwdVisit v{image_rsrc(img + b * P.n_units, nb), image_rsrc(mu + b * mu_stride, nb), R.scale, 1.0, 0.0};
+    walk<DIM>(P, R, v);
+    sino[b * P.n_rays + r] = (float)v.acc;
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_adjoint_att(DevPlan P, const float* __restrict__ sino,
+                                                         const float* __restrict__ mu, int64_t mu_stride, float* img)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.n_rays) return;
+    const int64_t b = blockIdx.y;
+    const float g = sino[b * P.n_rays + r];
+    if (g == 0.0f) return;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];
+    AttAdjVisit v{img + b * P.n_units, image_rsrc(mu + b * mu_stride, (int32_t)(P.n_units * 4)), R.scale, (double)g,
+                  1.0};
+    walk<DIM>(P, R, v);
+}
+
 __global__ void k_reset_counter(unsigned long long* c)
 {
     if (threadIdx.x == 0) *c = 0ull;
@@ -374,6 +482,8 @@ xrt_status dispatch(const DevPlan& P, dim3 grid, hipStream_t s, Args... args)
 }
 
 template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M>; } };
+template <int D, int M> struct FwdAttK { static auto fn() { return k_forward_att<D, M>; } };
+template <int D, int M> struct AdjAttK { static auto fn() { return k_adjoint_att<D, M>; } };
 template <int D, int M> struct ScatK { static auto fn() { return k_scatter<D, M>; } };
 template <int D, int M> struct CntK { static auto fn() { return k_counts<D, M>; } };
 template <int D, int M> struct HitK { static auto fn() { return k_hits<D, M>; } };
@@ -477,6 +587,22 @@ uint32_t forward_batch_blocks_per_cu()
         return 4;
     }
     return nb > 0 ? (uint32_t)nb : 1u;
+}
+
+xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride, float* sino,
+                              int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    return dispatch<FwdAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, mu, mu_stride, sino);
+}
+
+xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float* mu, int64_t mu_stride, float* img,
+                              int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    xrt_status st = launch_fill_zero(img, P.n_units * (int64_t)batch, s);
+    if (st != XRT_OK) return st;
+    return dispatch<AdjAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, mu, mu_stride, img);
 }
 
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,

@@ -82,6 +82,8 @@ def _lib():
         lib.xrt_batch_destroy.argtypes = [vp]
         lib.xrt_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         lib.xrt_batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        lib.xrt_forward_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
+        lib.xrt_adjoint_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
         lib.xrt_scan_workspace.argtypes = [i64]
         lib.xrt_scan_workspace.restype = i64
         lib.xrt_offsets_from_counts.argtypes = [i64, vp, vp, vp, vp]
@@ -238,6 +240,36 @@ class Plan:
         self._dev_check(out)
         _check(_lib().xrt_adjoint(self._h, _ptr(sino), _ptr(out), b, ADJ[mode], _stream(self.device)),
                "xrt_adjoint")
+        return out
+
+    def _mu(self, mu: torch.Tensor, b: int) -> int:
+        self._dev_check(mu)
+        lead, mb = self._batch(mu, self.image_shape)
+        if mb not in (1, b):
+            raise ValueError("mu must hold one attenuation map or one per image")
+        return int(mb == b and b > 1)
+
+    def forward_attenuated(self, img: torch.Tensor, mu: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Attenuated transform of img with attenuation map(s) mu (see xrt_forward_attenuated)."""
+        self._dev_check(img)
+        lead, b = self._batch(img, self.image_shape)
+        per = self._mu(mu, b)
+        if out is None:
+            out = torch.empty(lead + tuple(self.sino_shape), dtype=torch.float32, device=img.device)
+        self._dev_check(out)
+        _check(_lib().xrt_forward_attenuated(self._h, _ptr(img), _ptr(mu), per, _ptr(out), b, _stream(self.device)),
+               "xrt_forward_attenuated")
+        return out
+
+    def adjoint_attenuated(self, sino: torch.Tensor, mu: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._dev_check(sino)
+        lead, b = self._batch(sino, self.sino_shape)
+        per = self._mu(mu, b)
+        if out is None:
+            out = torch.empty(lead + tuple(self.image_shape), dtype=torch.float32, device=sino.device)
+        self._dev_check(out)
+        _check(_lib().xrt_adjoint_attenuated(self._h, _ptr(sino), _ptr(mu), per, _ptr(out), b, _stream(self.device)),
+               "xrt_adjoint_attenuated")
         return out
 
     def hit_counts(self, first: int = 0, n: int | None = None, eps: float = 0.0) -> torch.Tensor:

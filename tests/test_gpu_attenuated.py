@@ -1,0 +1,105 @@
+"""GPU: the attenuated transform (the paper's generalised transform with the SPECT
+weight) and its adjoint against the FP64 oracle on every scan kind, the plain transform
+when mu = 0, shared and per-image maps, the adjoint identity, and sampled rays of the
+256^3 cone workload."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import tests.helpers as H
+from oracle import core as ocore
+from oracle import geometry as ogeom
+from paper_2006_00686_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+KINDS = ["par2d", "fan2d_flat", "fan2d_arc", "par3d", "cone_flat", "helical", "cone_arc"]
+
+
+@pytest.fixture(scope="module")
+def X():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_00686_amd import xrt
+    xrt.library()
+    return xrt
+
+
+def _scan(name):
+    return {n: (g, s) for n, g, s in H.small_scans()}[name]
+
+
+def _bar(grid, scan, img, mu):
+    p, th = ogeom.expand(scan)
+    ref = ocore.forward_att_lines(grid, p, th, img.astype(np.float64), mu.astype(np.float64))
+    scl = ocore.forward_att_lines(grid, p, th, np.abs(img).astype(np.float64), mu.astype(np.float64))
+    return ref, scl
+
+
+@pytest.mark.parametrize("name", KINDS)
+def test_attenuated_parity(X, name):
+    grid, scan = _scan(name)
+    plan = X.Plan(grid, scan)
+    rng = np.random.default_rng(21)
+    shape = tuple(plan.image_shape)
+    img = rng.uniform(0, 1, size=(2,) + shape).astype(np.float32)
+    mu = rng.uniform(0, 0.3, size=(2,) + shape).astype(np.float32)
+    got = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu).to(DEV)).cpu().numpy()
+    for b in range(2):
+        ref, scl = _bar(grid, scan, img[b], mu[b])
+        H.assert_within_bar(got[b], ref, scl, what=f"attenuated {name} image {b}")
+    # one map shared by both images
+    shared = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu[0]).to(DEV)).cpu().numpy()
+    ref, scl = _bar(grid, scan, img[1], mu[0])
+    H.assert_within_bar(shared[1], ref, scl, what=f"attenuated {name} shared map")
+    # adjoint against the oracle's
+    w = rng.normal(size=tuple(plan.sino_shape)).astype(np.float32)
+    adj = plan.adjoint_attenuated(torch.from_numpy(w).to(DEV), torch.from_numpy(mu[0]).to(DEV)).cpu().numpy()
+    p, th = ogeom.expand(scan)
+    aref = ocore.adjoint_att_lines(grid, p, th, w.astype(np.float64), mu[0].astype(np.float64))
+    ascl = ocore.adjoint_att_lines(grid, p, th, np.abs(w).astype(np.float64), mu[0].astype(np.float64))
+    H.assert_within_bar(adj, aref, ascl, what=f"attenuated adjoint {name}")
+
+
+def test_zero_attenuation_is_the_transform(X):
+    grid, scan = _scan("cone_flat")
+    plan = X.Plan(grid, scan)
+    img = torch.from_numpy(inputs.random_image(tuple(plan.image_shape), 5)).to(DEV)
+    a = plan.forward_attenuated(img, torch.zeros_like(img)).cpu().numpy()
+    b = plan.forward(img).cpu().numpy()
+    ref, scl = H.forward_bar(grid, scan, img.cpu().numpy())
+    H.assert_within_bar(a, b, scl, rtol=1e-6, what="mu = 0")
+
+
+def test_attenuated_adjoint_identity(X):
+    grid, scan = _scan("helical")
+    plan = X.Plan(grid, scan)
+    rng = np.random.default_rng(8)
+    f = torch.from_numpy(rng.uniform(0, 1, tuple(plan.image_shape)).astype(np.float32)).to(DEV)
+    mu = torch.from_numpy(rng.uniform(0, 0.2, tuple(plan.image_shape)).astype(np.float32)).to(DEV)
+    w = torch.from_numpy(rng.uniform(0, 1, tuple(plan.sino_shape)).astype(np.float32)).to(DEV)
+    lhs = float((plan.forward_attenuated(f, mu).double() * w.double()).sum())
+    rhs = float((f.double() * plan.adjoint_attenuated(w, mu).double()).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_cone_256_attenuated_sampled(X):
+    cfg = inputs.workload("cone_256")
+    plan = X.Plan(cfg["grid"], cfg["scan"])
+    img = inputs.random_image(tuple(plan.image_shape), 9)
+    mu = (0.01 * inputs.random_image(tuple(plan.image_shape), 10)).astype(np.float32)
+    got = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu).to(DEV)).cpu().numpy().ravel()
+    rng = np.random.default_rng(11)
+    views = np.sort(rng.choice(len(cfg["scan"]["angles"]), 3, replace=False))
+    sub = dict(cfg["scan"])
+    sub["angles"] = np.asarray(cfg["scan"]["angles"])[views]
+    p, th = ogeom.expand(sub)
+    pick = rng.choice(p.shape[0], 1500, replace=False)
+    nr, nc = cfg["scan"]["nrows"], cfg["scan"]["ncols"]
+    vloc, rem = np.divmod(pick, nr * nc)
+    gidx = views[vloc] * nr * nc + rem
+    ref = ocore.forward_att_lines(cfg["grid"], p[pick], th[pick], img.astype(np.float64), mu.astype(np.float64))
+    scl = ocore.forward_att_lines(cfg["grid"], p[pick], th[pick], np.abs(img).astype(np.float64),
+                                  mu.astype(np.float64))
+    H.assert_within_bar(got[gidx], ref, scl, what="cone_256 attenuated sampled")
