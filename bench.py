@@ -245,6 +245,27 @@ def main():
                 "fwd_ms": round(t_fwd, 4), "adj_ms": round(t_adj, 4),
                 "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # the attenuated transform (SPECT weight) of the same workload, mu = 0.01 per unit length
+    log("[bench] attenuated transform")
+    gen = torch.Generator(device=dev).manual_seed(13)
+    d_mu = torch.rand(tuple(plan.image_shape), generator=gen, device=dev) * 0.01
+    plan.forward_attenuated(d_img, d_mu, out=d_sino)
+    plan.adjoint_attenuated(d_sino, d_mu, out=d_back)
+    ea = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ea[0].record(stream)
+    for _ in range(2):
+        plan.forward_attenuated(d_img, d_mu, out=d_sino)
+    ea[1].record(stream)
+    for _ in range(2):
+        plan.adjoint_attenuated(d_sino, d_mu, out=d_back)
+    ea[2].record(stream)
+    torch.cuda.synchronize()
+    attenuated = {"forward_ms": round(ea[0].elapsed_time(ea[1]) / 2, 3),
+                  "adjoint_ms": round(ea[1].elapsed_time(ea[2]) / 2, 3), "adjoint": "scatter",
+                  "mu": "uniform [0, 0.01) per unit length"}
+    log(f"[bench] attenuated {attenuated}")
+
     batched = None
     if not args.no_batched:
         log("[bench] batched launch: 16 uneven cone/helical problems")
@@ -285,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "learned": learned,
         "batched": batched,
+        "attenuated": attenuated,
     }
     print(json.dumps(out), flush=True)
 
