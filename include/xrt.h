@@ -269,8 +269,10 @@ int64_t xrt_csr_transpose_workspace(int64_t n_cols);
 /* Transpose of a CSR matrix with n_rows rows, n_cols columns and nnz nonzeros (d_off int64
  * [n_rows+1], d_col int32 [nnz] in [0, n_cols), d_val float [nnz]) into d_t_off int64
  * [n_cols+1], d_t_col int32 [nnz], d_t_val float [nnz]; the entries of every transposed
- * row are sorted by column, so the result is unique (deterministic).  Sizes up to 2^31-1
- * rows and columns; d_work int64 [work_len >= xrt_csr_transpose_workspace(n_cols)]. */
+ * row are sorted by column, so the result is unique (deterministic).  Entries whose
+ * column lies outside [0, n_cols) are dropped (d_t_off[n_cols] then counts the others).
+ * d_off must be a valid row-offset array for d_col / d_val.  Sizes up to 2^31-1 rows and
+ * columns; d_work int64 [work_len >= xrt_csr_transpose_workspace(n_cols)]. */
 xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t* d_off, const int32_t* d_col,
                              const float* d_val, int64_t* d_t_off, int32_t* d_t_col, float* d_t_val, int64_t* d_work,
                              int64_t work_len, void* stream);

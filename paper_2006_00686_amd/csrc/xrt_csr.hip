@@ -98,18 +98,21 @@ __global__ __launch_bounds__(kSB) void k_zero_i32(int32_t* __restrict__ p, int64
     for (int64_t i = (int64_t)blockIdx.x * kSB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSB) p[i] = 0;
 }
 
-// nonzeros per column (integer atomics: the totals do not depend on their order)
-__global__ __launch_bounds__(kSB) void k_csr_count_cols(const int32_t* __restrict__ col, int64_t nnz,
+// nonzeros per column (integer atomics: the totals do not depend on their order);
+// entries whose column lies outside [0, n_cols) are dropped here and in k_csr_fill
+__global__ __launch_bounds__(kSB) void k_csr_count_cols(const int32_t* __restrict__ col, int64_t nnz, int64_t n_cols,
                                                         int32_t* __restrict__ counts)
 {
-    for (int64_t e = (int64_t)blockIdx.x * kSB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kSB)
-        atomicAdd(counts + col[e], 1);
+    for (int64_t e = (int64_t)blockIdx.x * kSB + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kSB) {
+        const int32_t c = col[e];
+        if (c >= 0 && c < n_cols) atomicAdd(counts + c, 1);
+    }
 }
 
 // place every nonzero of row r into its column's segment (order within a segment is
 // fixed afterwards by k_csr_sort_cols)
 __global__ __launch_bounds__(kSB) void k_csr_fill(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
-                                                  const float* __restrict__ val, int64_t n_rows,
+                                                  const float* __restrict__ val, int64_t n_rows, int64_t n_cols,
                                                   const int64_t* __restrict__ t_off, int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ t_col, float* __restrict__ t_val)
 {
@@ -117,6 +120,7 @@ __global__ __launch_bounds__(kSB) void k_csr_fill(const int64_t* __restrict__ of
     if (r >= n_rows) return;
     for (int64_t e = off[r]; e < off[r + 1]; ++e) {
         const int32_t c = col[e];
+        if (c < 0 || c >= n_cols) continue;
         const int64_t pos = t_off[c] + atomicAdd(cursor + c, 1);
         t_col[pos] = (int32_t)r;
         t_val[pos] = val[e];
@@ -302,13 +306,13 @@ xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const 
     int64_t* sw = d_work + (n_cols + 1);
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_capped(n_cols + 1)), dim3(kSB), 0, s, counts, n_cols + 1);
     if (nnz > 0)
-        hipLaunchKernelGGL(k_csr_count_cols, dim3(grid_capped(nnz)), dim3(kSB), 0, s, d_col, nnz, counts);
+        hipLaunchKernelGGL(k_csr_count_cols, dim3(grid_capped(nnz)), dim3(kSB), 0, s, d_col, nnz, n_cols, counts);
     xrt_status st = scan(n_cols, counts, d_t_off, sw, s);
     if (st != XRT_OK) return st;
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_capped(n_cols + 1)), dim3(kSB), 0, s, counts, n_cols + 1);
     if (n_rows > 0)
-        hipLaunchKernelGGL(k_csr_fill, dim3(grid_of(n_rows)), dim3(kSB), 0, s, d_off, d_col, d_val, n_rows, d_t_off,
-                           counts, d_t_col, d_t_val);
+        hipLaunchKernelGGL(k_csr_fill, dim3(grid_of(n_rows)), dim3(kSB), 0, s, d_off, d_col, d_val, n_rows, n_cols,
+                           d_t_off, counts, d_t_col, d_t_val);
     if (n_cols > 0)
         hipLaunchKernelGGL(k_csr_sort_cols, dim3(grid_of(n_cols)), dim3(kSB), 0, s, d_t_off, n_cols, d_t_col, d_t_val);
     return hip_fail(hipGetLastError(), "xrt_csr_transpose launch");
