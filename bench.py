@@ -149,11 +149,21 @@ def batched_bench(torch, dev, steps: int, tuning: dict):
 
     eager()
     t_eager = timed(eager)
+
+    # the forward alone: one persistent launch over the queue vs one launch per plan
+    t_fwd_batch = timed(lambda: bg.batch.forward(bg.imgs, out=bg.sinos))
+
+    def fwd_each():
+        for p, im, sn in zip(plans, bg.imgs, bg.sinos):
+            p.forward(im, out=sn)
+
+    t_fwd_each = timed(fwd_each)
     rays = sum(p.n_rays for p in plans)
     dims = sorted({tuple(p.image_shape) for p in plans}, key=lambda d: -int(np.prod(d)))
     return {"workload": cfg["name"], "members": len(plans), "rays": rays, "volumes_zyx": [list(d) for d in dims],
             "ms_per_step": round(t_graph, 3), "mrays_per_s": round(rays / (t_graph * 1e-3) / 1e6, 1),
-            "per_plan_launches_ms": round(t_eager, 3), "launch": tuning,
+            "per_plan_launches_ms": round(t_eager, 3), "forward_persistent_ms": round(t_fwd_batch, 3),
+            "forward_per_plan_ms": round(t_fwd_each, 3), "launch": tuning,
             "data": "synthetic: seeded uniform volumes"}
 
 
