@@ -278,9 +278,9 @@ xrt_status xrt_csr_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, const 
                              int64_t work_len, void* stream);
 
 /* d_y[b][r] = sum over row r of val * d_x[b][col] for b < batch (d_x float [batch][n_cols],
- * d_y float [batch][n_rows]); FP64 accumulation in the row's order (deterministic).  A
- * column index outside [0, n_cols) reads 0.  batch * n_cols * 4 bytes must fit in 31 bits
- * (XRT_E_ARG otherwise). */
+ * d_y float [batch][n_rows]); one wavefront per row and 8 images per pass, FP64 partial
+ * sums reduced in a fixed order (deterministic).  A column index outside [0, n_cols)
+ * reads 0.  batch * n_cols * 4 bytes must fit in 31 bits (XRT_E_ARG otherwise). */
 xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col, const float* d_val,
                         int32_t batch, const float* d_x, float* d_y, void* stream);
 
@@ -292,8 +292,8 @@ xrt_status xrt_interleave(int64_t n, int32_t batch, int32_t to_interleaved, cons
 /* xrt_csr_spmv on batch-interleaved vectors: d_y_il[r][b] = sum over row r of
  * val * d_x_il[col][b] (d_x_il float [n_cols][batch], d_y_il float [n_rows][batch], batch in
  * [1, 64]); one wavefront per row with the images in its lanes, so each nonzero reads the
- * batch's values of one unit from contiguous memory.  Same arithmetic and order as
- * xrt_csr_spmv. */
+ * batch's values of one unit from contiguous memory; FP64 accumulation in the row's
+ * order (deterministic). */
 xrt_status xrt_csr_spmv_interleaved(int64_t n_rows, int64_t n_cols, const int64_t* d_off, const int32_t* d_col,
                                    const float* d_val, int32_t batch, const float* d_x_il, float* d_y_il, void* stream);
 

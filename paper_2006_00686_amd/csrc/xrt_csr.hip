@@ -149,16 +149,26 @@ __global__ __launch_bounds__(kSB) void k_csr_sort_cols(const int64_t* __restrict
     }
 }
 
-// y[b][r] = sum_e val[e] x[b][col[e]] over row r, FP64 accumulation in the row's order;
-// one lane per row, BB images per lane.  The gathers are bounds-checked buffer loads
-// (a column index outside the input reads 0).
+// y[b][r] = sum_e val[e] x[b][col[e]] over row r, kSpmvBB images per pass: one wavefront
+// per row, lanes striding over the row's nonzeros (coalesced index and value loads), FP64
+// partial sums reduced across the wavefront in a fixed butterfly order (deterministic).
+// The gathers are bounds-checked buffer loads (a column outside the input reads 0).
 constexpr int kSpmvBB = 8;
+constexpr int kRowsPerBlock = kSB / 64;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
 
 __global__ __launch_bounds__(kSB) void k_csr_spmv(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                                                   const float* __restrict__ val, int64_t n_rows, int32_t n_cols,
                                                   int32_t batch, const float* __restrict__ x, float* __restrict__ y)
 {
-    const int64_t r = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    const int32_t lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (r >= n_rows) return;
     const int32_t b0 = blockIdx.y * kSpmvBB;
     const uint64_t a = (uint64_t)x;
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(kSB) void k_csr_spmv(const int64_t* __restrict__ of
 #pragma unroll
     for (int q = 0; q < kSpmvBB; ++q) acc[q] = 0.0;
     const int64_t e1 = off[r + 1];
-    for (int64_t e = off[r]; e < e1; ++e) {
+    for (int64_t e = off[r] + lane; e < e1; e += 64) {
         const int32_t c = col[e];
         const double v = (double)val[e];
 #pragma unroll
@@ -181,8 +191,10 @@ __global__ __launch_bounds__(kSB) void k_csr_spmv(const int64_t* __restrict__ of
         }
     }
 #pragma unroll
-    for (int q = 0; q < kSpmvBB; ++q)
-        if (b0 + q < batch) y[(int64_t)(b0 + q) * n_rows + r] = (float)acc[q];
+    for (int q = 0; q < kSpmvBB; ++q) {
+        const double t = wave_sum(acc[q]);
+        if (lane == 0 && b0 + q < batch) y[(int64_t)(b0 + q) * n_rows + r] = (float)t;
+    }
 }
 
 // Batch-interleaved product: x_il [n_cols][batch], y_il [n_rows][batch] (batch <= 64).
@@ -322,12 +334,12 @@ xrt_status xrt_csr_spmv(int64_t n_rows, int64_t n_cols, const int64_t* d_off, co
                         int32_t batch, const float* d_x, float* d_y, void* stream)
 {
     if (n_rows < 0 || n_cols < 0 || batch < 1 || batch > 65535 * kSpmvBB || !d_off || !d_x || !d_y ||
-        (int64_t)batch * n_cols * 4 > INT32_MAX - 16) {
+        (int64_t)batch * n_cols * 4 > INT32_MAX - 16 || (n_rows + kRowsPerBlock - 1) / kRowsPerBlock > INT32_MAX) {
         set_error("xrt_csr_spmv: bad argument or input too large for 32-bit offsets");
         return XRT_E_ARG;
     }
     if (n_rows == 0) return XRT_OK;
-    const dim3 g(grid_of(n_rows), (unsigned)((batch + kSpmvBB - 1) / kSpmvBB));
+    const dim3 g((unsigned)((n_rows + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)((batch + kSpmvBB - 1) / kSpmvBB));
     hipLaunchKernelGGL(k_csr_spmv, g, dim3(kSB), 0, (hipStream_t)stream, d_off, d_col, d_val, n_rows, (int32_t)n_cols,
                        batch, d_x, d_y);
     return hip_fail(hipGetLastError(), "xrt_csr_spmv launch");

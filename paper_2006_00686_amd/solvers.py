@@ -37,8 +37,9 @@ class PlanOperator:
 class MatrixOperator:
     """A and A^T as products with the stored projection matrix (xrt.SparseMatrix).
 
-    Batches of 2..64 problems run interleaved ([unit][problem]: each nonzero reads the
-    batch's values from contiguous memory) through buffers kept between calls."""
+    Batches of 9..64 problems run interleaved ([unit][problem]: each nonzero reads the
+    batch's values from contiguous memory) through buffers kept between calls; smaller
+    batches use the wavefront-per-row product directly."""
 
     def __init__(self, A):
         self.A = A
@@ -57,7 +58,7 @@ class MatrixOperator:
         batch = x.numel() // int(np.prod(in_shape))
         if out is None:
             out = torch.empty((batch,) + tuple(out_shape), dtype=torch.float32, device=x.device)
-        if batch < 2 or batch > 64:
+        if batch <= 8 or batch > 64:
             return M.matmul(x, out=out)
         bi, bo = self._il(batch, x.device)
         xi, yo = (bi, bo) if M is self.A else (bo, bi)
@@ -108,14 +109,19 @@ class _Dots:
 
 
 def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
-         finish=None, stall_checks: int = 0, stall_ratio: float = 0.999) -> tuple[torch.Tensor, SolveInfo]:
+         finish=None, stall_checks: int = 0, stall_ratio: float = 0.999,
+         graph: bool = False) -> tuple[torch.Tensor, SolveInfo]:
     """CGLS (x0 = 0): minimises ||op(x) - g|| for every batch member.
 
     Stops after `iters` iterations or once every member's recursive residual satisfies
     ||r|| <= tol ||g||.  `finish(z)` maps the iterate to the image (the preconditioner for
     right-preconditioned CGLS).  With a tolerance, the iteration is abandoned (info.failure)
     when the worst residual is not finite, or, if stall_checks > 0, when it has not dropped
-    below stall_ratio times its value stall_checks checks earlier."""
+    below stall_ratio times its value stall_checks checks earlier.
+
+    graph=True captures `check_every` iterations in a HIP graph once (after a first
+    iteration run directly, which loads every kernel) and replays it between checks: the
+    same kernels in the same order, so the same results, without one launch per kernel."""
     batch = g.shape[0]
     dev = g.device
     torch.cuda.synchronize(dev)
@@ -131,7 +137,8 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
     dots(s, s, gamma)
     dots(g, g, gg)
     info = SolveInfo()
-    for it in range(1, iters + 1):
+
+    def step():
         op.apply(p, out=q)
         dots(q, q, delta)
         X.vec_axpy_ratio(gamma, delta, 1.0, p, x, batch)     # x += (gamma / delta) p
@@ -139,23 +146,43 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
         op.adjoint(r, out=s)
         dots(s, s, gamma_new)
         X.vec_xpby_ratio(gamma_new, gamma, s, p, batch)      # p = s + (gamma' / gamma) p
-        gamma, gamma_new = gamma_new, gamma
+        torch.mul(gamma_new, 1.0, out=gamma)                  # gamma = gamma' (a kernel)
+
+    def check() -> bool:
+        """Record the worst residual; True when the iteration ends here."""
+        dots(r, r, rr)
+        worst = float(torch.sqrt(rr / gg).max().item())
+        info.rel_residual.append(worst)
+        if worst <= tol:
+            info.converged = True
+            return True
+        if not math.isfinite(worst):
+            info.failure = "nonfinite"
+            return True
+        h = info.rel_residual
+        if stall_checks and len(h) > stall_checks and h[-1] > stall_ratio * h[-1 - stall_checks]:
+            info.failure = "stall"
+            return True
+        return False
+
+    k = max(1, int(check_every))
+    it, g_obj = 0, None
+    while it < iters:
+        n = min(k - it % k, iters - it)        # iterations up to the next check
+        if graph and it > 0 and n == k:
+            if g_obj is None:
+                g_obj = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g_obj):
+                    for _ in range(k):
+                        step()
+            g_obj.replay()
+        else:
+            for _ in range(n):
+                step()
+        it += n
         info.iterations = it
-        if tol is not None and (it % check_every == 0 or it == iters):
-            dots(r, r, rr)
-            rel = torch.sqrt(rr / gg)
-            worst = float(rel.max().item())
-            info.rel_residual.append(worst)
-            if worst <= tol:
-                info.converged = True
-                break
-            if not math.isfinite(worst):
-                info.failure = "nonfinite"
-                break
-            h = info.rel_residual
-            if stall_checks and len(h) > stall_checks and h[-1] > stall_ratio * h[-1 - stall_checks]:
-                info.failure = "stall"
-                break
+        if tol is not None and check():
+            break
     out = finish(x) if finish is not None else x
     torch.cuda.synchronize(dev)
     info.seconds = time.perf_counter() - t0
@@ -163,17 +190,17 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
 
 
 def pcgls(op, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
-          fallback: bool = True, stall_checks: int = 4):
+          fallback: bool = True, stall_checks: int = 4, graph: bool = False):
     """Right-preconditioned CGLS: min ||A P z - g||, image f = P z.
 
     With a tolerance and fallback=True, a preconditioned run whose worst residual becomes
     non-finite or stalls is discarded and plain CGLS solves the problem from x0 = 0
     (info.fallback and info.failure are set; info.seconds covers both runs)."""
     x, info = cgls(RightPreconditioned(op, P), g, iters, tol, check_every, finish=P.apply,
-                   stall_checks=stall_checks if tol is not None else 0)
+                   stall_checks=stall_checks if tol is not None else 0, graph=graph)
     if info.failure is None or not fallback:
         return x, info
-    x, plain = cgls(op, g, iters, tol, check_every)
+    x, plain = cgls(op, g, iters, tol, check_every, graph=graph)
     plain.fallback = True
     plain.failure = info.failure
     plain.seconds += info.seconds

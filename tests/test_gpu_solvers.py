@@ -148,3 +148,23 @@ def test_cgls_is_reproducible(mods):
     a, _ = solvers.cgls(op, g, iters=25)
     b, _ = solvers.cgls(op, g, iters=25)
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_graph_replayed_cgls_matches_eager(mods, k):
+    solvers, xrt = mods
+    grid, scan, imgs = _small_problem()
+    plan = xrt.Plan(grid, scan)
+    op = solvers.PlanOperator(plan)
+    g = plan.forward(torch.from_numpy(imgs).to(DEV))
+    a, ia = solvers.cgls(op, g, 40, tol=1e-4, check_every=k)
+    b, ib = solvers.cgls(op, g, 40, tol=1e-4, check_every=k, graph=True)
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert ia.iterations == ib.iterations and ia.rel_residual == ib.rel_residual
+    # right-preconditioned, through the graph as well
+    from paper_2006_00686_amd.learned import ConvPreconditioner
+    P = ConvPreconditioner(DEV, seed=1, init_scale=0.05)
+    c, ic = solvers.pcgls(op, P, g, 30, tol=1e-4, check_every=k)
+    d, id_ = solvers.pcgls(op, P, g, 30, tol=1e-4, check_every=k, graph=True)
+    np.testing.assert_array_equal(c.cpu().numpy(), d.cpu().numpy())
+    assert ic.iterations == id_.iterations

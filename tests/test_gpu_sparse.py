@@ -114,10 +114,14 @@ def test_interleaved_product_matches(X, batch):
     xi = X.interleave(x, batch)
     np.testing.assert_array_equal(xi.cpu().numpy(), x.reshape(batch, -1).T.cpu().numpy())
     y = X.deinterleave(A.matmul_interleaved(xi, batch), batch, torch.empty_like(ref))
-    # same products in the same order: identical bits
-    np.testing.assert_array_equal(y.cpu().numpy(), ref.cpu().numpy())
+    # the same FP64 sums in a different order: equal to FP32 rounding
+    scl = A.matmul(x.abs()).cpu().numpy()
+    assert np.all(np.abs(y.cpu().numpy() - ref.cpu().numpy()) <= 1e-6 * scl + 1e-7)
+    # both forms are deterministic
+    np.testing.assert_array_equal(A.matmul(x).cpu().numpy(), ref.cpu().numpy())
     At = A.transpose()
     w = torch.from_numpy(rng.normal(size=(batch,) + tuple(plan.sino_shape)).astype(np.float32)).to(DEV)
     from paper_2006_00686_amd import solvers
     op = solvers.MatrixOperator(A)
-    np.testing.assert_array_equal(op.adjoint(w).cpu().numpy(), At.matmul(w).cpu().numpy())
+    ascl = At.matmul(w.abs()).cpu().numpy()
+    assert np.all(np.abs(op.adjoint(w).cpu().numpy() - At.matmul(w).cpu().numpy()) <= 1e-6 * ascl + 1e-7)
