@@ -102,21 +102,36 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64
 constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
 constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
 
+// The rays of one (view, detector column) that can cross a wave's pixel column, as
+// every lane of the wave needs them: the pixel's xy interval (tin, tout) of the ray
+// parameter, 1/tin and 1/tout in row bins, the source height and the column's offset in
+// the transposed sinogram.  One wave fills up to 64 records at once, one lane per
+// (view, column slot), and then walks them in lane order.
+struct ColRecs {
+    double tin[64], tout[64], sin[64], sout[64], sz[64];
+    int32_t g[64];
+};
+constexpr int kWaves = kBlock / 64;
+
 // One wave per voxel column (i, j) and z chunk; lane = voxel along z, KB per lane.
 // NR: bound on the rows a voxel's shadow covers in one detector column (from the plan).
 // ZR: the detector has a row with v = 0, whose rays lie in the plane z = Sz.
 // CULL (helical scans, where the detector sees a band of z at a time): a wave skips a
 // block of 64 voxels when none of them has a candidate row on the detector; skipped
 // rows are exactly the ones that would add nothing.
+// lg_slots: log2 of the column slots per view in one record pass (a bound on the
+// columns of a pixel's shadow, from the plan; wider shadows take further passes).
 template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
                                                          float* __restrict__ img,
                                                          const double* __restrict__ inv_v, int32_t zero_row,
-                                                         int32_t nzc, int32_t nlogical)
+                                                         int32_t nzc, int32_t nlogical, int32_t lg_slots)
 {
-    // 1/v of every row, followed by NR entries 0 for rows past the detector: their z
-    // interval (0, 0) lies before tin > 0, so they are never hit
-    extern __shared__ double s_iv[];
+    // per-wave records, then 1/v of every row followed by NR entries 0 for rows past
+    // the detector: their z interval (0, 0) lies before tin > 0, so they are never hit
+    extern __shared__ double s_dyn[];
+    ColRecs* const s_rec = reinterpret_cast<ColRecs*>(s_dyn);
+    double* const s_iv = s_dyn + kWaves * sizeof(ColRecs) / sizeof(double);
     for (int32_t r = threadIdx.x; r < P.n_rows + NR; r += kBlock) s_iv[r] = r < P.n_rows ? inv_v[r] : 0.0;
     __syncthreads();
 
@@ -126,17 +141,19 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
     const int32_t per = (int32_t)(gridDim.x >> 3);
     const int32_t L = (int32_t)(blockIdx.x & 7) * per + (int32_t)(blockIdx.x >> 3);
     if (L >= nlogical) return;
-    const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t colid = (int64_t)L * (kBlock / 64) + wave;
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int64_t colid = (int64_t)L * kWaves + wave;
     if (colid >= (int64_t)P.nx * P.ny * nzc) return;
     const int32_t zc = (int32_t)(colid % nzc);
     const int64_t ij = colid / nzc;
     const int32_t i = (int32_t)(ij % P.nx), j = (int32_t)(ij / P.nx);
+    ColRecs& R = s_rec[wave];
 
     // unit (k, j, i): x in [xa, xb), y in (ya, yb], z in (za, zb]  (Sec. 4.1 resolution)
     const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
+    const double vb = -P.vbase * idv;
     const int32_t kbase = zc * 64 * KB + lane;
     const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, P.n_rays * 4);
 
@@ -147,13 +164,16 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
         zb0[q] = P.pz0 - (double)(kbase + 64 * q) * P.pdz;   // top face of the lane's voxel q
     }
 
-    for (int32_t v = 0; v < P.n_views; ++v) {
-        const ViewGeom& V = P.views[v];
-        const double Sx = V.A[0], Sy = V.A[1], Sz = V.A[2];
+    const int32_t slot = lane & ((1 << lg_slots) - 1), vlane = lane >> lg_slots;
+    for (int32_t v0 = 0; v0 < P.n_views; v0 += 64 >> lg_slots) {
+        // this lane's view: detector columns whose rays can cross the pixel, from u of
+        // the four corners seen from the source, u = sdd^2 ((P - S).B) / ((P - S).E)
+        const int32_t v = v0 + vlane;
+        const bool vok = v < P.n_views;
+        const ViewGeom& V = P.views[vok ? v : P.n_views - 1];
+        const double Sx = V.A[0], Sy = V.A[1];
         const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
         const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
-        // detector columns whose rays can cross the pixel: u of the four corners seen
-        // from the source, u = sdd^2 ((P - S).B) / ((P - S).E)
         double umin = kInf, umax = -kInf;
 #pragma unroll
         for (int cnr = 0; cnr < 4; ++cnr) {
@@ -164,73 +184,98 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
         }
         const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
         const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
-        for (int32_t c = c0; c <= c1; ++c) {
-            const double u = fma((double)c, P.du, P.ubase);
+        for (int32_t cb = c0;; cb += 1 << lg_slots) {
+            if (__builtin_amdgcn_ballot_w64(vok && cb <= c1) == 0) break;
             // C_low / C_up of the pixel in xy, shared by every ray of column c
+            const int32_t c = cb + slot;
+            bool ok = vok && c <= c1;
             double tin = -kInf, tout = kInf;
-            axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
-            axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
-            if (!(tin < tout)) continue;
-            // first candidate row: the smallest v = rel / tau of the voxel over
-            // tau in (tin, tout), in bin units
-            const double sin_ = rcp_fast(tin) * idv, sout = rcp_fast(tout) * idv;
-            const double vb = -P.vbase * idv;
-            const int32_t gcol4 = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
+            if (ok) {
+                const double u = fma((double)c, P.du, P.ubase);
+                axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
+                axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
+                ok = tin < tout;
+            }
+            const uint64_t live = __builtin_amdgcn_ballot_w64(ok);
+            if (ok) {
+                const int32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
+                R.tin[at] = tin;
+                R.tout[at] = tout;
+                R.sin[at] = rcp_fast(tin) * idv;
+                R.sout[at] = rcp_fast(tout) * idv;
+                R.sz[at] = V.A[2];
+                R.g[at] = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int32_t nrec = __builtin_popcountll(live);
+            for (int32_t e = 0; e < nrec; ++e) {
+                const double tin_ = R.tin[e], tout_ = R.tout[e], sin_ = R.sin[e], sout = R.sout[e], Sz = R.sz[e];
+                const int32_t gcol4 = R.g[e];
 #pragma unroll
-            for (int q = 0; q < KB; ++q) {
-                const int32_t k = kbase + 64 * q;
-                const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
-                const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
-                // rows outside the voxel's range fail C_low < C_up below on their own
-                // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
-                const int32_t r0 = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
-                if constexpr (CULL) {
-                    // rows past the detector are zero padding; a voxel whose rows all lie
-                    // above the first row (by half a bin, far beyond the error of the
-                    // estimates) has no hit in rows r0 = 0 ..
-                    const double vtop = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                    const bool live = k < P.nz && r0 < P.n_rows && vtop >= -0.5;
-                    if (__builtin_amdgcn_ballot_w64(live) == 0) continue;
-                }
-                auto row = [&](int e, double& l, float& g) {
-                    const int32_t r = r0 + e;
-                    double lo = tin, hi = tout;
-                    if (ZR && r == zero_row) {
-                        if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
-                    } else {
-                        const double iv = s_iv[r];
-                        const double t0 = rel0 * iv, t1 = rel1 * iv;
-                        lo = fmax(lo, fmin(t0, t1));
-                        hi = fmin(hi, fmax(t0, t1));
+                for (int q = 0; q < KB; ++q) {
+                    // first candidate row: the smallest v = rel / tau of the voxel over
+                    // tau in (tin, tout), in bin units
+                    const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
+                    const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
+                    // rows outside the voxel's range fail C_low < C_up below on their own
+                    // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
+                    const int32_t r0 = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
+                    if constexpr (CULL) {
+                        // rows past the detector are zero padding; a voxel whose rows all
+                        // lie above the first row (by half a bin, far beyond the error of
+                        // the estimates) has no hit in rows r0 = 0 ..
+                        const int32_t k = kbase + 64 * q;
+                        const double vtop = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                        const bool any = k < P.nz && r0 < P.n_rows && vtop >= -0.5;
+                        if (__builtin_amdgcn_ballot_w64(any) == 0) continue;
                     }
-                    const bool hit = hi > lo && k < P.nz;   // C_low < C_up
-                    // a candidate that is not hit reads 0 (out of range): its (finite,
-                    // non-positive) length then adds nothing
-                    l = hi - lo;
-                    g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                      gsrc, hit ? gcol4 + 4 * r : kOutOfRange, 0, 0));
-                };
-                double l0, l1;
-                float g0, g1;
-                row(0, l0, g0);
-                row(1, l1, g1);
-                acc[q] = fma((double)g0, l0, acc[q]);
-                acc[q] = fma((double)g1, l1, acc[q]);
-                if constexpr (NR > 2) {
-                    // only where some lane's shadow spans more than one bin (whole waves
-                    // skip it often enough that evaluating it always is slower)
-                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                    if (vhi + kRangeSlack >= (double)(r0 + 2)) {
+                    // lanes past the volume (k >= nz) compute values that are never stored
+                    auto row = [&](int ei, double& l, float& g) {
+                        const int32_t r = r0 + ei;
+                        double lo = tin_, hi = tout_;
+                        if (ZR && r == zero_row) {
+                            if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
+                        } else {
+                            const double iv = s_iv[r];
+                            const double t0 = rel0 * iv, t1 = rel1 * iv;
+                            lo = fmax(lo, fmin(t0, t1));
+                            hi = fmin(hi, fmax(t0, t1));
+                        }
+                        // C_low < C_up; a candidate that is not hit reads 0 (out of range):
+                        // its (finite, non-positive) length then adds nothing
+                        l = hi - lo;
+                        g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                          gsrc, hi > lo ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                    };
+                    double l0, l1;
+                    float g0, g1;
+                    row(0, l0, g0);
+                    row(1, l1, g1);
+                    acc[q] = fma((double)g0, l0, acc[q]);
+                    acc[q] = fma((double)g1, l1, acc[q]);
+                    if constexpr (NR > 2) {
+                        // only where some lane's shadow spans more than one bin (whole
+                        // waves skip it often enough that evaluating it always is slower)
+                        const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                        if (vhi + kRangeSlack >= (double)(r0 + 2)) {
 #pragma unroll
-                        for (int e = 2; e < NR; ++e) {
-                            double le;
-                            float ge;
-                            row(e, le, ge);
-                            acc[q] = fma((double)ge, le, acc[q]);
+                            for (int ei = 2; ei < NR; ++ei) {
+                                double le;
+                                float ge;
+                                row(ei, le, ge);
+                                acc[q] = fma((double)ge, le, acc[q]);
+                            }
                         }
                     }
                 }
             }
+            // every lane has read the records before the next pass rewrites them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 #pragma unroll
@@ -329,13 +374,13 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
         return XRT_E_SIZE;
     }
     const int64_t launched = (nlog + 7) / 8 * 8;
-    const size_t lds = (size_t)(P.n_rows + NR) * sizeof(double);
+    const size_t lds = kWaves * sizeof(ColRecs) + (size_t)(P.n_rows + NR) * sizeof(double);
     if (p->zero_row >= 0)
         hipLaunchKernelGGL((k_cone_gather<KB, NR, true, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
-                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs);
     else
         hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
-                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog);
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 

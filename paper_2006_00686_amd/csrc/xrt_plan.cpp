@@ -307,6 +307,7 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
 {
     const DevPlan& D = p->dp;
     p->zero_row = -1;
+    p->gather_lgs = 2;
     p->helical = 0;
     for (const ViewGeom& V : views) p->helical |= V.A[2] != views[0].A[2] ? 1 : 0;
     // The detector columns that see a pixel are the interval between its corners' u
@@ -351,6 +352,14 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
             return XRT_OK;
         }
         p->gather_nr = (int32_t)nr;
+        // columns of one pixel's shadow: it subtends at most diag / hmin radians, and a
+        // radian spans at most rho^2 / sdd along the flat detector; the gather fills its
+        // per-view column records in slots of the next power of two of that bound + 2
+        // (a wider shadow only costs a further pass)
+        const double ncol = std::floor(diag / hmin * rho * rho / D.sdd / D.du) + 2.0;
+        int lgs = 0;
+        while (lgs < 6 && (double)(1 << lgs) < ncol) ++lgs;
+        p->gather_lgs = lgs;
     }
     std::vector<double> inv((size_t)D.n_rows);
     for (int r = 0; r < D.n_rows; ++r) {
