@@ -122,7 +122,7 @@ constexpr int kWaves = kBlock / 64;
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
 template <int KB, int NR, bool ZR, bool CULL>
-__global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
                                                          float* __restrict__ img,
                                                          const double* __restrict__ inv_v, int32_t zero_row,
                                                          int32_t nzc, int32_t nlogical, int32_t lg_slots)
@@ -165,26 +165,28 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
     }
 
     const int32_t slot = lane & ((1 << lg_slots) - 1), vlane = lane >> lg_slots;
-    for (int32_t v0 = 0; v0 < P.n_views; v0 += 64 >> lg_slots) {
-        // this lane's view: detector columns whose rays can cross the pixel, from u of
-        // the four corners seen from the source, u = sdd^2 ((P - S).B) / ((P - S).E)
-        const int32_t v = v0 + vlane;
-        const bool vok = v < P.n_views;
-        const ViewGeom& V = P.views[vok ? v : P.n_views - 1];
-        const double Sx = V.A[0], Sy = V.A[1];
-        const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
-        const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
-        double umin = kInf, umax = -kInf;
+    for (int32_t v0 = 0; v0 < P.n_views; v0 += 64 >> lg_slots)
+        for (int32_t pass = 0;; ++pass) {
+            // this lane's view: detector columns whose rays can cross the pixel, from u of
+            // the four corners seen from the source, u = sdd^2 ((P - S).B) / ((P - S).E);
+            // recomputed per pass so that none of it stays live across the voxel loop
+            const int32_t v = v0 + vlane;
+            const bool vok = v < P.n_views;
+            const ViewGeom& V = P.views[vok ? v : P.n_views - 1];
+            const double Sx = V.A[0], Sy = V.A[1];
+            const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
+            const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
+            double umin = kInf, umax = -kInf;
 #pragma unroll
-        for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = (cnr & 1) ? ax1 : ax0, py = (cnr & 2) ? ay1 : ay0;
-            const double u = sdd2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-        }
-        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
-        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
-        for (int32_t cb = c0;; cb += 1 << lg_slots) {
+            for (int cnr = 0; cnr < 4; ++cnr) {
+                const double px = (cnr & 1) ? ax1 : ax0, py = (cnr & 2) ? ay1 : ay0;
+                const double u = sdd2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
+                umin = fmin(umin, u);
+                umax = fmax(umax, u);
+            }
+            const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
+            const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
+            const int32_t cb = c0 + (pass << lg_slots);
             if (__builtin_amdgcn_ballot_w64(vok && cb <= c1) == 0) break;
             // C_low / C_up of the pixel in xy, shared by every ray of column c
             const int32_t c = cb + slot;
@@ -214,6 +216,30 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
             for (int32_t e = 0; e < nrec; ++e) {
                 const double tin_ = R.tin[e], tout_ = R.tout[e], sin_ = R.sin[e], sout = R.sout[e], Sz = R.sz[e];
                 const int32_t gcol4 = R.g[e];
+                // length of row r in the voxel between z offsets rel0 < rel1 (lanes past the
+                // volume, k >= nz, compute values that are never stored)
+                auto row = [&](int32_t r, double rel0, double rel1, double& l, float& g) {
+                    double lo = tin_, hi = tout_;
+                    if (ZR && r == zero_row) {
+                        if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
+                    } else {
+                        const double iv = s_iv[r];
+                        const double t0 = rel0 * iv, t1 = rel1 * iv;
+                        lo = fmax(lo, fmin(t0, t1));
+                        hi = fmin(hi, fmax(t0, t1));
+                    }
+                    // C_low < C_up; a candidate that is not hit reads 0 (out of range): its
+                    // (finite, non-positive) length then adds nothing
+                    l = hi - lo;
+                    g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                      gsrc, hi > lo ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                };
+                // rows r0 and r0 + 1 of every voxel of the lane first (their loads all in
+                // flight together), then the rows beyond where some shadow reaches them
+                int32_t r0[KB];
+                double l0[KB], l1[KB];
+                float g0[KB], g1[KB];
+                bool more[KB];
 #pragma unroll
                 for (int q = 0; q < KB; ++q) {
                     // first candidate row: the smallest v = rel / tau of the voxel over
@@ -222,50 +248,42 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
                     const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
                     // rows outside the voxel's range fail C_low < C_up below on their own
                     // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
-                    const int32_t r0 = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
+                    r0[q] = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
+                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
+                    more[q] = NR > 2 && vhi + kRangeSlack >= (double)(r0[q] + 2);
                     if constexpr (CULL) {
                         // rows past the detector are zero padding; a voxel whose rows all
                         // lie above the first row (by half a bin, far beyond the error of
                         // the estimates) has no hit in rows r0 = 0 ..
                         const int32_t k = kbase + 64 * q;
-                        const double vtop = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                        const bool any = k < P.nz && r0 < P.n_rows && vtop >= -0.5;
-                        if (__builtin_amdgcn_ballot_w64(any) == 0) continue;
-                    }
-                    // lanes past the volume (k >= nz) compute values that are never stored
-                    auto row = [&](int ei, double& l, float& g) {
-                        const int32_t r = r0 + ei;
-                        double lo = tin_, hi = tout_;
-                        if (ZR && r == zero_row) {
-                            if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
-                        } else {
-                            const double iv = s_iv[r];
-                            const double t0 = rel0 * iv, t1 = rel1 * iv;
-                            lo = fmax(lo, fmin(t0, t1));
-                            hi = fmin(hi, fmax(t0, t1));
+                        const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5;
+                        if (__builtin_amdgcn_ballot_w64(any) == 0) {
+                            l0[q] = l1[q] = 0.0;
+                            g0[q] = g1[q] = 0.0f;
+                            more[q] = false;
+                            continue;
                         }
-                        // C_low < C_up; a candidate that is not hit reads 0 (out of range):
-                        // its (finite, non-positive) length then adds nothing
-                        l = hi - lo;
-                        g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                          gsrc, hi > lo ? gcol4 + 4 * r : kOutOfRange, 0, 0));
-                    };
-                    double l0, l1;
-                    float g0, g1;
-                    row(0, l0, g0);
-                    row(1, l1, g1);
-                    acc[q] = fma((double)g0, l0, acc[q]);
-                    acc[q] = fma((double)g1, l1, acc[q]);
-                    if constexpr (NR > 2) {
-                        // only where some lane's shadow spans more than one bin (whole
-                        // waves skip it often enough that evaluating it always is slower)
-                        const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                        if (vhi + kRangeSlack >= (double)(r0 + 2)) {
+                    }
+                    row(r0[q], rel0, rel1, l0[q], g0[q]);
+                    row(r0[q] + 1, rel0, rel1, l1[q], g1[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    acc[q] = fma((double)g0[q], l0[q], acc[q]);
+                    acc[q] = fma((double)g1[q], l1[q], acc[q]);
+                }
+                if constexpr (NR > 2) {
+                    // only where some lane's shadow spans more than one bin (whole waves
+                    // skip it often enough that evaluating it always is slower)
+#pragma unroll
+                    for (int q = 0; q < KB; ++q) {
+                        if (more[q]) {
+                            const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
 #pragma unroll
                             for (int ei = 2; ei < NR; ++ei) {
                                 double le;
                                 float ge;
-                                row(ei, le, ge);
+                                row(r0[q] + ei, rel0, rel1, le, ge);
                                 acc[q] = fma((double)ge, le, acc[q]);
                             }
                         }
@@ -277,7 +295,6 @@ __global__ __launch_bounds__(kBlock) void k_cone_gather(DevPlan P, const float* 
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-    }
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
         const int32_t k = kbase + 64 * q;
@@ -390,8 +407,7 @@ xrt_status launch_nr_c(const xrt_plan* p, const float* gT, float* img, hipStream
     const int32_t nz = p->dp.nz;
     if (nz <= 64) return launch_kb<1, NR, CULL>(p, gT, img, s);
     if (nz <= 128) return launch_kb<2, NR, CULL>(p, gT, img, s);
-    if (nz <= 256) return launch_kb<4, NR, CULL>(p, gT, img, s);
-    return launch_kb<8, NR, CULL>(p, gT, img, s);
+    return launch_kb<4, NR, CULL>(p, gT, img, s);   // deeper volumes: further z chunks
 }
 
 template <int NR>
