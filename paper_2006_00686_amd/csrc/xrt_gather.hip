@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
     const double vb = -P.vbase * idv;
     const int32_t kbase = zc * 64 * KB + lane;
-    const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, P.n_rays * 4);
+    const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, (P.n_rays + kGatherPad) * 4);
 
     double acc[KB], zb0[KB];
 #pragma unroll
@@ -216,9 +216,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int32_t e = 0; e < nrec; ++e) {
                 const double tin_ = R.tin[e], tout_ = R.tout[e], sin_ = R.sin[e], sout = R.sout[e], Sz = R.sz[e];
                 const int32_t gcol4 = R.g[e];
-                // length of row r in the voxel between z offsets rel0 < rel1 (lanes past the
+                // C_up - C_low of row r in the voxel between z offsets rel0 < rel1: positive
+                // iff C_low < C_up (hit), else finite and non-positive (lanes past the
                 // volume, k >= nz, compute values that are never stored)
-                auto row = [&](int32_t r, double rel0, double rel1, double& l, float& g) {
+                auto len = [&](int32_t r, double rel0, double rel1) {
                     double lo = tin_, hi = tout_;
                     if (ZR && r == zero_row) {
                         if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
@@ -228,20 +229,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         lo = fmax(lo, fmin(t0, t1));
                         hi = fmin(hi, fmax(t0, t1));
                     }
-                    // C_low < C_up; a candidate that is not hit reads 0 (out of range): its
-                    // (finite, non-positive) length then adds nothing
-                    l = hi - lo;
-                    g = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                      gsrc, hi > lo ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                    return hi - lo;
                 };
-                // rows r0 and r0 + 1 of every voxel of the lane first (their loads all in
-                // flight together), then the rows beyond where some shadow reaches them
+                // per voxel q of the lane: rows r0 and r0 + 1 (one 8-byte load, out of range
+                // when neither row is hit; a row that is not hit contributes 0), then the
+                // rows beyond where some shadow reaches them
                 int32_t r0[KB];
                 double l0[KB], l1[KB];
                 float g0[KB], g1[KB];
                 bool more[KB];
-#pragma unroll
-                for (int q = 0; q < KB; ++q) {
+                auto head = [&](int q) {
                     // first candidate row: the smallest v = rel / tau of the voxel over
                     // tau in (tin, tout), in bin units
                     const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
@@ -257,37 +254,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         // the estimates) has no hit in rows r0 = 0 ..
                         const int32_t k = kbase + 64 * q;
                         const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5;
-                        if (__builtin_amdgcn_ballot_w64(any) == 0) {
-                            l0[q] = l1[q] = 0.0;
-                            g0[q] = g1[q] = 0.0f;
-                            more[q] = false;
-                            continue;
-                        }
+                        if (__builtin_amdgcn_ballot_w64(any) == 0) return false;
                     }
-                    row(r0[q], rel0, rel1, l0[q], g0[q]);
-                    row(r0[q] + 1, rel0, rel1, l1[q], g1[q]);
-                }
-#pragma unroll
-                for (int q = 0; q < KB; ++q) {
+                    l0[q] = len(r0[q], rel0, rel1);
+                    l1[q] = len(r0[q] + 1, rel0, rel1);
+                    const bool h0 = l0[q] > 0.0, h1 = l1[q] > 0.0;
+                    const int32_t off = h0 || h1 ? gcol4 + 4 * r0[q] : kOutOfRange;
+                    const uint32_t a = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off, 0, 0);
+                    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off + 4, 0, 0);
+                    g0[q] = h0 ? __builtin_bit_cast(float, a) : 0.0f;
+                    g1[q] = h1 ? __builtin_bit_cast(float, b) : 0.0f;
+                    return true;
+                };
+                auto body = [&](int q) {
                     acc[q] = fma((double)g0[q], l0[q], acc[q]);
                     acc[q] = fma((double)g1[q], l1[q], acc[q]);
-                }
-                if constexpr (NR > 2) {
-                    // only where some lane's shadow spans more than one bin (whole waves
-                    // skip it often enough that evaluating it always is slower)
+                };
+                // only where some lane's shadow spans more than one bin (whole waves skip it
+                // often enough that evaluating it always is slower)
+                auto tail = [&](int q) {
+                    if (NR > 2 && more[q]) {
+                        const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
 #pragma unroll
-                    for (int q = 0; q < KB; ++q) {
-                        if (more[q]) {
-                            const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
-#pragma unroll
-                            for (int ei = 2; ei < NR; ++ei) {
-                                double le;
-                                float ge;
-                                row(r0[q] + ei, rel0, rel1, le, ge);
-                                acc[q] = fma((double)ge, le, acc[q]);
-                            }
+                        for (int ei = 2; ei < NR; ++ei) {
+                            const int32_t r = r0[q] + ei;
+                            const double le = len(r, rel0, rel1);
+                            // a row that is not hit reads 0 (out of range)
+                            const float ge = __builtin_bit_cast(
+                                float, __builtin_amdgcn_raw_buffer_load_b32(
+                                           gsrc, le > 0.0 ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                            acc[q] = fma((double)ge, le, acc[q]);
                         }
                     }
+                };
+                if constexpr (CULL) {
+                    // helical scans: most voxels of a record are culled, so each is done
+                    // in full where it is not
+#pragma unroll
+                    for (int q = 0; q < KB; ++q)
+                        if (head(q)) {
+                            body(q);
+                            tail(q);
+                        }
+                } else {
+                    // the loads of every voxel of the lane in flight together
+#pragma unroll
+                    for (int q = 0; q < KB; ++q) head(q);
+#pragma unroll
+                    for (int q = 0; q < KB; ++q) body(q);
+#pragma unroll
+                    for (int q = 0; q < KB; ++q) tail(q);
                 }
             }
             // every lane has read the records before the next pass rewrites them

@@ -26,6 +26,9 @@ struct ViewGeom {         // FP64 per-view vectors, see RayMode
 
 // Everything a projection kernel needs, passed by value as a kernel argument.
 constexpr int kMaxBatch = 32;   // members of one xrt_batch
+// floats after the gather's transposed sinogram: its 8-byte row-pair loads may read one
+// element past the last ray (the value is then discarded)
+constexpr int kGatherPad = 64;
 
 struct DevPlan {
     int32_t dim;          // 2 or 3

@@ -314,7 +314,7 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
     // coordinates only when the pixel is in front of the source; require it of the
     // whole image box for every view, otherwise the plan uses the scatter adjoint.
     // sinogram byte offsets are 32-bit in the gather kernel
-    p->gather_ok = D.n_rays <= (int64_t)(INT32_MAX - 15) / 4 ? 1 : 0;
+    p->gather_ok = D.n_rays + kGatherPad <= (int64_t)(INT32_MAX - 15) / 4 ? 1 : 0;
     for (const ViewGeom& V : views) {
         const double en = std::sqrt(V.E[0] * V.E[0] + V.E[1] * V.E[1] + V.E[2] * V.E[2]);
         for (int cnr = 0; cnr < 8; ++cnr) {
@@ -374,10 +374,10 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
     xrt_status st = upload(inv, &p->d_invwz);
     if (st != XRT_OK) return st;
     void* ws = nullptr;
-    hipError_t e = hipMalloc(&ws, (size_t)D.n_rays * sizeof(float));
+    hipError_t e = hipMalloc(&ws, (size_t)(D.n_rays + kGatherPad) * sizeof(float));
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        set_error("hipMalloc of the %lld-float adjoint workspace failed: %s", (long long)D.n_rays,
+        set_error("hipMalloc of the %lld-float adjoint workspace failed: %s", (long long)D.n_rays + kGatherPad,
                   hipGetErrorString(e));
         return XRT_E_NOMEM;
     }
