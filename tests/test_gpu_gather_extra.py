@@ -1,6 +1,8 @@
 """GPU: the voxel-driven cone adjoint where a voxel's shadow spans many detector rows
-(fine rows: bound of 6-8 candidate rows per column) and on a long helix over a short
-volume (most views see a band of z that misses most voxels)."""
+(fine rows: bound of 6-8 candidate rows per column), many detector columns (fine
+columns: 32 or 64 column slots per view, and shadows wider than 64 columns that take
+further record passes), and on a long helix over a short volume (most views see a band
+of z that misses most voxels)."""
 import numpy as np
 import pytest
 
@@ -29,7 +31,13 @@ def _scans():
     nv = 96
     helix = dict(kind="cone_flat", angles=np.arange(nv) * 2 * np.pi * 4 / nv, ncols=36, nrows=6, du=1.2, dv=1.5,
                  u0=0.0, v0=0.0, sod=60.0, sdd=90.0, view_z=np.linspace(-20.0, 20.0, nv))
-    return [("fine_rows", g, fine), ("long_helix", gh, helix)]
+    gc = dict(nx=12, ny=10, nz=8, dx=1.0, dy=1.0, dz=1.0, cx=0.3, cy=-0.2, cz=0.1)
+    mid_cols = dict(kind="cone_flat", angles=np.linspace(0.1, 2 * np.pi, 10, endpoint=False), ncols=200, nrows=9,
+                    du=0.1, dv=1.4, u0=0.03, v0=0.2, sod=100.0, sdd=150.0)
+    fine_cols = dict(kind="cone_flat", angles=np.linspace(0.2, 2 * np.pi, 8, endpoint=False), ncols=1000, nrows=9,
+                     du=0.02, dv=1.4, u0=0.011, v0=0.2, sod=100.0, sdd=150.0)
+    return [("fine_rows", g, fine), ("long_helix", gh, helix), ("mid_cols", gc, mid_cols),
+            ("fine_cols", gc, fine_cols)]
 
 
 @pytest.mark.parametrize("name,grid,scan", _scans(), ids=[s[0] for s in _scans()])
