@@ -216,6 +216,25 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
 xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,
                                   float* d_img, int32_t batch, void* stream);
 
+/* Per-ray weighted transform (Introduction, eq. generalizedRadontransform, PET case: the
+ * weight does not depend on the position along the ray, so the generalised transform is
+ * the X-ray transform times a weight given per ray).  d_w: float32 weights in sinogram
+ * layout, one set for all images (w_per_image = 0) or one per image.
+ * Forward: d_sino = w * (A d_img), the weight applied to the FP64 line integral before
+ * rounding.  Adjoint: d_img = A^T (w * d_sino), the weight applied where each kernel reads
+ * a sinogram value (mode as in xrt_adjoint, same summation order).  Same layouts and
+ * errors as xrt_forward / xrt_adjoint; d_w must not be NULL (XRT_E_ARG). */
+xrt_status xrt_forward_weighted(xrt_plan* plan, const float* d_img, const float* d_w, int32_t w_per_image,
+                                float* d_sino, int32_t batch, void* stream);
+xrt_status xrt_adjoint_weighted(xrt_plan* plan, const float* d_sino, const float* d_w, int32_t w_per_image,
+                                float* d_img, int32_t batch, int32_t mode, void* stream);
+
+/* Transmission of every ray through attenuation maps: d_w[b][ray] = exp(-(A d_mu[b])[ray]),
+ * the PET attenuation weight of a map given per unit length in the image layout (batch
+ * maps in, batch sets of weights out).  The line integral is rounded to float32 before
+ * the exponential (relative error below |integral| * 6e-8).  Errors as xrt_forward. */
+xrt_status xrt_ray_transmission(xrt_plan* plan, const float* d_mu, float* d_w, int32_t batch, void* stream);
+
 /* ---- launch shape of the forward projection (tuning; results do not depend on it) ----
  * packet_cols = 0: a wavefront takes 64 consecutive rays in (view, row, column) order;
  * 64, 32 or 16: a wavefront takes a packet of packet_cols detector columns x

@@ -127,6 +127,24 @@ def adjoint_att_lines(g: dict, p, th, sino, mu, nthreads=None):
     return img.reshape(image_shape(g))
 
 
+def forward_weighted_lines(g: dict, p, th, img, w, nthreads=None):
+    """PET form of the generalised transform (Introduction, eq. generalizedRadontransform
+    with a weight that does not depend on t): the weight of each ray times its X-ray
+    transform.  w: one weight per line."""
+    return np.asarray(w, dtype=np.float64).ravel() * forward_lines(g, p, th, img, nthreads)
+
+
+def adjoint_weighted_lines(g: dict, p, th, sino, w, nthreads=None):
+    """Transpose of forward_weighted_lines: the plain adjoint of w * sino."""
+    ws = np.asarray(w, dtype=np.float64).ravel() * np.asarray(sino, dtype=np.float64).ravel()
+    return adjoint_lines(g, p, th, ws, nthreads)
+
+
+def transmission_lines(g: dict, p, th, mu, nthreads=None):
+    """exp(-integral of mu along each line): the PET attenuation weight of the map mu."""
+    return np.exp(-forward_lines(g, p, th, mu, nthreads))
+
+
 def ray_hits_line(g: dict, p, th, eps=0.0):
     """(indices, lengths) of one ray, sorted by 1D index; lengths > eps."""
     lib = _load()
@@ -175,6 +193,21 @@ def forward_att(g: dict, scan: dict, img, mu, nthreads=None):
 def adjoint_att(g: dict, scan: dict, sino, mu, nthreads=None):
     p, th = geometry.expand(scan)
     return adjoint_att_lines(g, p, th, sino, mu, nthreads)
+
+
+def forward_weighted(g: dict, scan: dict, img, w, nthreads=None):
+    p, th = geometry.expand(scan)
+    return forward_weighted_lines(g, p, th, img, w, nthreads).reshape(geometry.sino_shape(scan))
+
+
+def adjoint_weighted(g: dict, scan: dict, sino, w, nthreads=None):
+    p, th = geometry.expand(scan)
+    return adjoint_weighted_lines(g, p, th, sino, w, nthreads)
+
+
+def transmission(g: dict, scan: dict, mu, nthreads=None):
+    p, th = geometry.expand(scan)
+    return transmission_lines(g, p, th, mu, nthreads).reshape(geometry.sino_shape(scan))
 
 
 def adjoint(g: dict, scan: dict, sino, nthreads=None):

@@ -24,9 +24,11 @@ namespace {
 constexpr int kTile = 32;
 constexpr int kBlock = 256;
 
-// gT[v][c][r] = g[v][r][c] * |d_{c,r}|, |d|^2 = sdd^2 + u_c^2 + v_r^2 (orthogonal frame).
+// gT[v][c][r] = g[v][r][c] * w[v][r][c] * |d_{c,r}|, |d|^2 = sdd^2 + u_c^2 + v_r^2 (orthogonal
+// frame); w: per-ray weights (the PET form of the generalised transform), or none.
 __global__ __launch_bounds__(kBlock) void k_cone_sino_prep(DevPlan P, const float* __restrict__ g,
-                                                           float* __restrict__ gT, int32_t rblocks)
+                                                           float* __restrict__ gT, int32_t rblocks,
+                                                           const float* __restrict__ wt)
 {
     __shared__ float tile[kTile][kTile + 1];
     const int32_t v = blockIdx.y / rblocks;
@@ -39,8 +41,9 @@ __global__ __launch_bounds__(kBlock) void k_cone_sino_prep(DevPlan P, const floa
         if (r < P.n_rows && c < P.n_cols) {
             const double u = fma((double)c, P.du, P.ubase);
             const double w = fma((double)r, P.dv, P.vbase);
-            const float x = g[((int64_t)v * P.n_rows + r) * P.n_cols + c];
-            tile[yy][tx] = (float)((double)x * sqrt(sdd2 + u * u + w * w));
+            const int64_t ray = ((int64_t)v * P.n_rows + r) * P.n_cols + c;
+            const double x = (double)g[ray] * (wt != nullptr ? (double)wt[ray] : 1.0);
+            tile[yy][tx] = (float)(x * sqrt(sdd2 + u * u + w * w));
         }
     }
     __syncthreads();
@@ -323,9 +326,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // view the pixel's shadow on the detector gives the candidate bins; each candidate ray
 // is clipped against the pixel (C_low < C_up of eq. conditions_2D_1, half-open faces)
 // and adds g * len.  Deterministic: fixed view and bin order.
+// wt: per-ray weights applied to the sinogram values (the PET form), or none.
 template <int MODE, int BB>
 __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __restrict__ sino,
-                                                      float* __restrict__ img, int32_t batch)
+                                                      float* __restrict__ img, int32_t batch,
+                                                      const float* __restrict__ wt, int64_t wt_stride)
 {
     const int32_t pix = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (pix >= P.nx * P.ny) return;
@@ -387,7 +392,11 @@ __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __r
             const int64_t r = (int64_t)v * P.n_cols + c;
 #pragma unroll
             for (int q = 0; q < BB; ++q)
-                if (b0 + q < batch) acc[q] = fma((double)sino[(int64_t)(b0 + q) * P.n_rays + r], len, acc[q]);
+                if (b0 + q < batch) {
+                    double g = (double)sino[(int64_t)(b0 + q) * P.n_rays + r];
+                    if (wt != nullptr) g *= (double)wt[(int64_t)(b0 + q) * wt_stride + r];
+                    acc[q] = fma(g, len, acc[q]);
+                }
         }
     }
 #pragma unroll
@@ -434,20 +443,24 @@ xrt_status launch_nr(const xrt_plan* p, const float* gT, float* img, hipStream_t
 
 }  // namespace
 
-xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s)
+xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s,
+                                   const float* wt, int64_t wt_stride)
 {
     const DevPlan& P = p->dp;
     constexpr int BB = 8;
     const dim3 grid((unsigned)((P.nx * P.ny + kBlock - 1) / kBlock), (unsigned)((batch + BB - 1) / BB));
     switch (P.mode) {
         case MODE_PARALLEL:
-            hipLaunchKernelGGL((k_gather2d<MODE_PARALLEL, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            hipLaunchKernelGGL((k_gather2d<MODE_PARALLEL, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
+                               wt_stride);
             break;
         case MODE_DIVERGENT:
-            hipLaunchKernelGGL((k_gather2d<MODE_DIVERGENT, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            hipLaunchKernelGGL((k_gather2d<MODE_DIVERGENT, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
+                               wt_stride);
             break;
         case MODE_ARC:
-            hipLaunchKernelGGL((k_gather2d<MODE_ARC, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch);
+            hipLaunchKernelGGL((k_gather2d<MODE_ARC, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
+                               wt_stride);
             break;
         default:
             set_error("no gather adjoint for ray lists");
@@ -457,14 +470,14 @@ xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* 
 }
 
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
-                                      hipStream_t s)
+                                      hipStream_t s, const float* wt, int64_t wt_stride)
 {
     const DevPlan& P = p->dp;
     const int32_t rblocks = (P.n_rows + kTile - 1) / kTile;
     const dim3 pgrid((unsigned)((P.n_cols + kTile - 1) / kTile), (unsigned)(rblocks * P.n_views));
     for (int b = 0; b < batch; ++b) {
         hipLaunchKernelGGL(k_cone_sino_prep, pgrid, dim3(kBlock), 0, s, P, sino + (int64_t)b * P.n_rays,
-                           p->d_gT, rblocks);
+                           p->d_gT, rblocks, wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr);
         xrt_status st = hip_fail(hipGetLastError(), "sinogram prep launch");
         if (st != XRT_OK) return st;
         float* out = img + (int64_t)b * P.n_units;

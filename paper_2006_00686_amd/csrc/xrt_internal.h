@@ -128,8 +128,9 @@ void set_error(const char* fmt, ...);
 xrt_status hip_fail(hipError_t e, const char* what);
 
 // Launchers (xrt_project.hip).
+// wt (optional): per-ray weights, wt_stride floats apart per image (0: shared)
 xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch,
-                          hipStream_t s);
+                          hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
 // One persistent launch over the members of a batch (host plan snapshots hp, device
 // copies d_plans, queue order, per-member images and sinograms).
 xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const DevPlan* d_plans, int32_t n,
@@ -142,7 +143,7 @@ xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float*
                               int batch, hipStream_t s);
 uint32_t forward_batch_blocks_per_cu();
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
-                                  hipStream_t s);
+                                  hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
 xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps,
                              int32_t* counts, hipStream_t s);
 xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps,
@@ -150,7 +151,10 @@ xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps,
 xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s);
 // Voxel-driven gather adjoint for flat-detector cone beams (xrt_gather.hip).
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
-                                      hipStream_t s);
+                                      hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
+// w[i] = exp(-x[i]) for n floats (in place allowed)
+xrt_status launch_transmission(float* w, const float* x, int64_t n, hipStream_t s);
 // Voxel-driven gather adjoint for 2D scans (xrt_gather.hip).
-xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s);
+xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s,
+                                   const float* wt = nullptr, int64_t wt_stride = 0);
 }  // namespace xrt

@@ -556,8 +556,10 @@ xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const flo
                               (hipStream_t)stream);
 }
 
-xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
-                       void* stream)
+namespace {
+
+xrt_status adjoint_impl(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
+                        void* stream, const float* wt, int64_t wt_stride)
 {
     if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
     if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
@@ -573,11 +575,49 @@ xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_
         return XRT_E_UNSUPPORTED;
     }
     DeviceGuard guard(plan->device);
+    const hipStream_t s = (hipStream_t)stream;
     if (mode != XRT_ADJ_SCATTER && cone_gather)
-        return launch_adjoint_cone_gather(plan, d_sino, d_img, batch, (hipStream_t)stream);
+        return launch_adjoint_cone_gather(plan, d_sino, d_img, batch, s, wt, wt_stride);
     if (mode != XRT_ADJ_SCATTER && gather2d)
-        return launch_adjoint_gather2d(plan, d_sino, d_img, batch, (hipStream_t)stream);
-    return launch_adjoint_scatter(plan, d_sino, d_img, batch, (hipStream_t)stream);
+        return launch_adjoint_gather2d(plan, d_sino, d_img, batch, s, wt, wt_stride);
+    return launch_adjoint_scatter(plan, d_sino, d_img, batch, s, wt, wt_stride);
+}
+
+}  // namespace
+
+xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
+                       void* stream)
+{
+    return adjoint_impl(plan, d_sino, d_img, batch, mode, stream, nullptr, 0);
+}
+
+xrt_status xrt_forward_weighted(xrt_plan* plan, const float* d_img, const float* d_w, int32_t w_per_image,
+                                float* d_sino, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_w || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_forward(plan, d_img, d_sino, batch, (hipStream_t)stream, d_w,
+                          w_per_image ? plan->dp.n_rays : 0);
+}
+
+xrt_status xrt_adjoint_weighted(xrt_plan* plan, const float* d_sino, const float* d_w, int32_t w_per_image,
+                                float* d_img, int32_t batch, int32_t mode, void* stream)
+{
+    if (!d_w) { set_error("null argument"); return XRT_E_ARG; }
+    return adjoint_impl(plan, d_sino, d_img, batch, mode, stream, d_w,
+                        plan != nullptr && w_per_image ? plan->dp.n_rays : 0);
+}
+
+xrt_status xrt_ray_transmission(xrt_plan* plan, const float* d_mu, float* d_w, int32_t batch, void* stream)
+{
+    if (!plan || !d_mu || !d_w) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    const hipStream_t s = (hipStream_t)stream;
+    xrt_status st = launch_forward(plan, d_mu, d_w, batch, s);
+    if (st != XRT_OK) return st;
+    return launch_transmission(d_w, d_w, plan->dp.n_rays * (int64_t)batch, s);
 }
 
 xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double eps, int32_t* d_counts,

@@ -295,7 +295,7 @@ __host__ __device__ inline uint64_t forward_threads(const DevPlan& P)
 // in consecutive addresses.
 template <int DIM, int MODE>
 __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const float* img, const float* imgT,
-                                            float* sino)
+                                            float* sino, const float* wt = nullptr)
 {
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
@@ -315,7 +315,9 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
     FwdVisit v{image_rsrc(base, (int32_t)(P.n_units * 4)), 0.0};
     walk<DIM>(P, R, v);
     v.consume();
-    sino[r] = (float)(v.acc * R.scale);
+    // wt: a per-ray weight (the PET form of the generalised transform), or none
+    const double w = wt != nullptr ? (double)wt[r] : 1.0;
+    sino[r] = (float)(v.acc * R.scale * w);
 }
 
 // nblocks: workgroups that carry rays; with xcd_remap the grid is rounded up to a
@@ -323,7 +325,8 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
                                                      const float* __restrict__ imgT, float* __restrict__ sino,
-                                                     uint32_t nblocks)
+                                                     uint32_t nblocks, const float* __restrict__ wt,
+                                                     int64_t wt_stride)
 {
     uint32_t blk = blockIdx.x;
     if (P.xcd_remap) {
@@ -333,7 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __re
     const int32_t r = forward_ray_of<MODE>(P, (uint64_t)blk * kBlock + threadIdx.x);
     if (r < 0) return;
     const int64_t b = blockIdx.y;
-    forward_one<DIM, MODE>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays);
+    forward_one<DIM, MODE>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays,
+                           wt != nullptr ? wt + b * wt_stride : nullptr);
 }
 
 // ------------------------------------------------------------------ batched (several plans)
@@ -445,18 +449,19 @@ __global__ __launch_bounds__(kBlock) void k_transpose_xy(const float* __restrict
     }
 }
 
+// wt: per-ray weights applied to the sinogram values (the PET form), or none.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_scatter(DevPlan P, const float* __restrict__ sino,
-                                                     float* img)
+                                                     float* img, const float* __restrict__ wt, int64_t wt_stride)
 {
     const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (r >= P.n_rays) return;
     const int64_t b = blockIdx.y;
-    const float g = sino[b * P.n_rays + r];
-    if (g == 0.0f) return;
+    const double g = (double)sino[b * P.n_rays + r] * (wt != nullptr ? (double)wt[b * wt_stride + r] : 1.0);
+    if (g == 0.0) return;
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
-    ScatterVisit v{img + b * P.n_units, (double)g * R.scale};
+    ScatterVisit v{img + b * P.n_units, g * R.scale};
     walk<DIM>(P, R, v);
 }
 
@@ -546,7 +551,8 @@ xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, 
     return hip_fail(hipGetLastError(), "transpose launch");
 }
 
-xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s)
+xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s,
+                          const float* wt, int64_t wt_stride)
 {
     const DevPlan& P = p->dp;
     const uint64_t nb64 = (forward_threads(P) + kBlock - 1) / kBlock;
@@ -554,12 +560,14 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
     const uint32_t nb = (uint32_t)nb64;
     const uint32_t grid = P.xcd_remap ? (nb + 7u) / 8u * 8u : nb;
     if (p->d_imgT == nullptr)
-        return dispatch<FwdK>(P, dim3(grid, (unsigned)batch), s, img, (const float*)nullptr, sino, nb);
+        return dispatch<FwdK>(P, dim3(grid, (unsigned)batch), s, img, (const float*)nullptr, sino, nb, wt,
+                              wt_stride);
     for (int b = 0; b < batch; ++b) {
         const float* im = img + (int64_t)b * P.n_units;
         xrt_status st = launch_transpose_xy(P, im, p->d_imgT, s);
         if (st != XRT_OK) return st;
-        st = dispatch<FwdK>(P, dim3(grid, 1u), s, im, (const float*)p->d_imgT, sino + (int64_t)b * P.n_rays, nb);
+        st = dispatch<FwdK>(P, dim3(grid, 1u), s, im, (const float*)p->d_imgT, sino + (int64_t)b * P.n_rays, nb,
+                            wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr, (int64_t)0);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;
@@ -643,12 +651,12 @@ xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float*
 }
 
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
-                                  hipStream_t s)
+                                  hipStream_t s, const float* wt, int64_t wt_stride)
 {
     const DevPlan& P = p->dp;
     xrt_status st = launch_fill_zero(img, P.n_units * (int64_t)batch, s);
     if (st != XRT_OK) return st;
-    return dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, img);
+    return dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, img, wt, wt_stride);
 }
 
 xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps, int32_t* counts,

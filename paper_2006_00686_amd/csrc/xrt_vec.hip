@@ -3,6 +3,8 @@
 // of two device-resident FP64 values, so a solver iteration never waits on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "xrt_internal.h"
 
 namespace xrt {
@@ -79,7 +81,23 @@ unsigned grid_for(int64_t n)
     return (unsigned)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
 }
 
+// w[i] = exp(-x[i]): the transmission of a ray through an attenuation map, from its line
+// integral (the PET weight of the generalised transform).
+__global__ __launch_bounds__(kVBlock) void k_transmission(float* w, const float* x, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+        w[i] = expf(-x[i]);
+}
+
 }  // namespace
+
+xrt_status launch_transmission(float* w, const float* x, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return XRT_OK;
+    const int64_t blocks = std::min<int64_t>((n + kVBlock - 1) / kVBlock, 65536);
+    hipLaunchKernelGGL(k_transmission, dim3((unsigned)blocks), dim3(kVBlock), 0, s, w, x, n);
+    return hip_fail(hipGetLastError(), "transmission launch");
+}
 }  // namespace xrt
 
 using namespace xrt;

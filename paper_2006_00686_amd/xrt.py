@@ -84,6 +84,9 @@ def _lib():
         lib.xrt_batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         lib.xrt_forward_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
         lib.xrt_adjoint_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
+        lib.xrt_forward_weighted.argtypes = [vp, vp, vp, i32, vp, i32, vp]
+        lib.xrt_adjoint_weighted.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp]
+        lib.xrt_ray_transmission.argtypes = [vp, vp, vp, i32, vp]
         lib.xrt_scan_workspace.argtypes = [i64]
         lib.xrt_scan_workspace.restype = i64
         lib.xrt_offsets_from_counts.argtypes = [i64, vp, vp, vp, vp]
@@ -270,6 +273,50 @@ class Plan:
         self._dev_check(out)
         _check(_lib().xrt_adjoint_attenuated(self._h, _ptr(sino), _ptr(mu), per, _ptr(out), b, _stream(self.device)),
                "xrt_adjoint_attenuated")
+        return out
+
+    def _weights(self, w: torch.Tensor, b: int) -> int:
+        """1 when w holds one set of per-ray weights per image, 0 for one shared set."""
+        self._dev_check(w)
+        n = w.numel() // self.n_rays if self.n_rays else 0
+        if w.numel() != n * self.n_rays or n not in (1, b):
+            raise ValueError("w must hold one weight per ray, shared or one set per image")
+        return int(n == b and b > 1)
+
+    def forward_weighted(self, img: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """w * (A img): the PET form of the generalised transform (see xrt_forward_weighted)."""
+        self._dev_check(img)
+        lead, b = self._batch(img, self.image_shape)
+        per = self._weights(w, b)
+        if out is None:
+            out = torch.empty(lead + tuple(self.sino_shape), dtype=torch.float32, device=img.device)
+        self._dev_check(out)
+        _check(_lib().xrt_forward_weighted(self._h, _ptr(img), _ptr(w), per, _ptr(out), b, _stream(self.device)),
+               "xrt_forward_weighted")
+        return out
+
+    def adjoint_weighted(self, sino: torch.Tensor, w: torch.Tensor, mode: str = "auto",
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+        """A^T (w * sino) (see xrt_adjoint_weighted)."""
+        self._dev_check(sino)
+        lead, b = self._batch(sino, self.sino_shape)
+        per = self._weights(w, b)
+        if out is None:
+            out = torch.empty(lead + tuple(self.image_shape), dtype=torch.float32, device=sino.device)
+        self._dev_check(out)
+        _check(_lib().xrt_adjoint_weighted(self._h, _ptr(sino), _ptr(w), per, _ptr(out), b, ADJ[mode],
+                                           _stream(self.device)), "xrt_adjoint_weighted")
+        return out
+
+    def ray_transmission(self, mu: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """exp(-(A mu)) per ray: the PET attenuation weights of map(s) mu."""
+        self._dev_check(mu)
+        lead, b = self._batch(mu, self.image_shape)
+        if out is None:
+            out = torch.empty(lead + tuple(self.sino_shape), dtype=torch.float32, device=mu.device)
+        self._dev_check(out)
+        _check(_lib().xrt_ray_transmission(self._h, _ptr(mu), _ptr(out), b, _stream(self.device)),
+               "xrt_ray_transmission")
         return out
 
     def hit_counts(self, first: int = 0, n: int | None = None, eps: float = 0.0) -> torch.Tensor:
