@@ -210,7 +210,9 @@ xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t h
  * for all images (mu_per_image = 0) or one per image.  Every hit piece of length len
  * contributes f exp(-A) (1 - exp(-mu len)) / mu (f len where mu = 0), A the attenuation
  * between the piece and the detector.  The adjoint is the exact transpose (ray-driven,
- * atomics: summation order not fixed).  Same layouts and errors as xrt_forward. */
+ * atomics: summation order not fixed).  Same layouts and errors as xrt_forward.  The
+ * forward's first call on a plan allocates a workspace of 2 n_units floats that the plan
+ * keeps (XRT_E_NOMEM if that fails); it interleaves each image with its map. */
 xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const float* d_mu, int32_t mu_per_image,
                                   float* d_sino, int32_t batch, void* stream);
 xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,

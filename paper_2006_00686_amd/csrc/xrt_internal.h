@@ -80,6 +80,9 @@ struct xrt_plan {
     // u axis runs along y (3D scans, owned by the plan), or NULL
     float* d_imgT;
     int32_t gather2d_ok;   // 2D scan whose image lies in front of every source position
+    // (f, mu) pairs of one image for the attenuated forward, allocated by its first call
+    // (2 n_units floats), or NULL
+    float* d_att;
 };
 
 // Several plans (same dimension and ray mode) projected together; the plans stay owned
@@ -154,6 +157,10 @@ xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, floa
                                       hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
 // w[i] = exp(-x[i]) for n floats (in place allowed)
 xrt_status launch_transmission(float* w, const float* x, int64_t n, hipStream_t s);
+// attenuated forward reading (f, mu) pairs from p->d_att (8 n_units bytes within 32-bit
+// offsets), one image after the other
+xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride,
+                                    float* sino, int batch, hipStream_t s);
 // Voxel-driven gather adjoint for 2D scans (xrt_gather.hip).
 xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s,
                                    const float* wt = nullptr, int64_t wt_stride = 0);

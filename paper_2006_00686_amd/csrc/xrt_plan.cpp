@@ -296,7 +296,8 @@ xrt_status upload(const std::vector<T>& h, void** d)
 void free_plan(xrt_plan* p)
 {
     if (!p) return;
-    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT})
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT,
+                    (void*)p->d_att})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -542,8 +543,23 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
     if (!plan || !d_img || !d_mu || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
     if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
     DeviceGuard guard(plan->device);
-    return launch_forward_att(plan, d_img, d_mu, mu_per_image ? plan->dp.n_units : 0, d_sino, batch,
-                              (hipStream_t)stream);
+    const int64_t mu_stride = mu_per_image ? plan->dp.n_units : 0;
+    // (f, mu) interleaved, so that each candidate takes one 8-byte load; the pairs of
+    // one image live in a plan workspace allocated here on first use
+    if (plan->dp.n_units * 8 <= (int64_t)INT32_MAX - 16) {
+        if (plan->d_att == nullptr) {
+            void* ws = nullptr;
+            if (hipMalloc(&ws, (size_t)plan->dp.n_units * 2 * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("hipMalloc of the %lld-float attenuated-forward workspace failed",
+                          (long long)plan->dp.n_units * 2);
+                return XRT_E_NOMEM;
+            }
+            plan->d_att = (float*)ws;
+        }
+        return launch_forward_att_pairs(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
+    }
+    return launch_forward_att(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
 }
 
 xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,

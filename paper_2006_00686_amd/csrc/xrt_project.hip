@@ -8,6 +8,8 @@
 // ask for packets of 32 x 2 or 16 x 4 detector cells instead, and an XCD-aware block
 // order).  A batch of plans runs as one persistent launch over a queue of ray chunks.
 // Image and sinogram data are float32; line integrals accumulate in FP64.
+#include <algorithm>
+
 #include "xrt_walk.h"
 
 namespace xrt {
@@ -228,6 +230,67 @@ struct AttFwdVisit {
     }
 };
 
+// AttFwdVisit reading (f, mu) pairs: one 8-byte load per candidate.
+struct AttFwdPairVisit {
+    static constexpr int32_t kIndexScale = 8;
+    __amdgpu_buffer_rsrc_t rp;   // (f, mu) pairs
+    double scale, A, acc;
+    float pf[3] = {0.0f, 0.0f, 0.0f}, pm[3] = {0.0f, 0.0f, 0.0f};
+    double pl[3] = {0.0, 0.0, 0.0};
+    __device__ __forceinline__ void ld(int32_t off, float& f, float& m)
+    {
+        f = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, off, 0, 0));
+        m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, off + 4, 0, 0));
+    }
+    // as AttFwdVisit::piece
+    __device__ __forceinline__ void piece(float f, float m, double l)
+    {
+        const double lp = fmax(l, 0.0) * scale, x = (double)m * lp;
+        const float w = att_weight(m, (float)lp, (float)x);
+        acc = fma((double)(f * __expf(-(float)A)), (double)w, acc);
+        A += x;
+    }
+    __device__ __forceinline__ void consume()
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) piece(pf[i], pm[i], pl[i]);
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        float f1, m1, f2, m2;
+        ld(I1, f1, m1);
+        ld(l2 > 0.0 ? I2 : kOutOfRange, f2, m2);
+        consume();
+        pf[0] = f1;
+        pm[0] = m1;
+        pl[0] = l1;
+        pf[1] = f2;
+        pm[1] = m2;
+        pl[1] = l2;
+        pf[2] = 0.0f;
+        pm[2] = 0.0f;
+        pl[2] = 0.0;
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        float f1, m1, f2, m2, f3, m3;
+        ld(I1, f1, m1);
+        ld(l2 > 0.0 ? I2 : kOutOfRange, f2, m2);
+        ld(l3 > 0.0 ? I3 : kOutOfRange, f3, m3);
+        consume();
+        pf[0] = f1;
+        pm[0] = m1;
+        pl[0] = l1;
+        pf[1] = f2;
+        pm[1] = m2;
+        pl[1] = l2;
+        pf[2] = f3;
+        pm[2] = m3;
+        pl[2] = l3;
+    }
+};
+
 struct AttAdjVisit {
     static constexpr int32_t kIndexScale = 1;
     float* img;
@@ -406,6 +469,31 @@ __global__ __launch_bounds__(kBlock) void k_forward_att(DevPlan P, const float* 
     sino[b * P.n_rays + r] = (float)v.acc;
 }
 
+// The attenuated forward of one image from its (f, mu) pairs.
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward_att_pairs(DevPlan P, const float* __restrict__ pairs,
+                                                               float* __restrict__ sino)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.n_rays) return;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];   // from the detector side back
+    AttFwdPairVisit v{image_rsrc(pairs, (int32_t)(P.n_units * 8)), R.scale, 0.0, 0.0};
+    walk<DIM>(P, R, v);
+    v.consume();
+    sino[r] = (float)v.acc;
+}
+
+// pairs[i] = (img[i], mu[i])
+__global__ __launch_bounds__(kBlock) void k_att_pairs(const float* __restrict__ img, const float* __restrict__ mu,
+                                                       float2* __restrict__ pairs, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        pairs[i] = make_float2(img[i], mu[i]);
+}
+
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_adjoint_att(DevPlan P, const float* __restrict__ sino,
                                                          const float* __restrict__ mu, int64_t mu_stride, float* img)
@@ -525,6 +613,7 @@ xrt_status dispatch(const DevPlan& P, dim3 grid, hipStream_t s, Args... args)
 
 template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M>; } };
 template <int D, int M> struct FwdAttK { static auto fn() { return k_forward_att<D, M>; } };
+template <int D, int M> struct FwdAttPairK { static auto fn() { return k_forward_att_pairs<D, M>; } };
 template <int D, int M> struct AdjAttK { static auto fn() { return k_adjoint_att<D, M>; } };
 template <int D, int M> struct ScatK { static auto fn() { return k_scatter<D, M>; } };
 template <int D, int M> struct CntK { static auto fn() { return k_counts<D, M>; } };
@@ -639,6 +728,23 @@ xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* 
 {
     const DevPlan& P = p->dp;
     return dispatch<FwdAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, mu, mu_stride, sino);
+}
+
+xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride,
+                                    float* sino, int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    const unsigned pblocks = (unsigned)std::min<int64_t>((P.n_units + kBlock - 1) / kBlock, 65536);
+    for (int b = 0; b < batch; ++b) {
+        hipLaunchKernelGGL(k_att_pairs, dim3(pblocks), dim3(kBlock), 0, s, img + (int64_t)b * P.n_units,
+                           mu + (int64_t)b * mu_stride, (float2*)p->d_att, P.n_units);
+        xrt_status st = hip_fail(hipGetLastError(), "attenuation pairs launch");
+        if (st != XRT_OK) return st;
+        st = dispatch<FwdAttPairK>(P, dim3(blocks_for(P.n_rays), 1u), s, (const float*)p->d_att,
+                                   sino + (int64_t)b * P.n_rays);
+        if (st != XRT_OK) return st;
+    }
+    return XRT_OK;
 }
 
 xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float* mu, int64_t mu_stride, float* img,
