@@ -13,9 +13,11 @@
 // column c; each voxel k then only adds the z interval of its 1-3 candidate rows.
 //
 // Work layout: one wavefront per voxel column (i, j) and z chunk, lane = voxel along z,
-// KB voxels per lane.  The sinogram is first transposed to [view][col][row] and scaled by
+// KB voxels per lane.  The per-(view, column) xy intervals are computed by the lanes in
+// parallel, 16 views x 4 column slots at a time, into records in LDS that the voxel loop
+// reads uniformly.  The sinogram is first transposed to [view][col][row] and scaled by
 // |d| (the ray parameter tau runs along d = detector cell - source, len = |d| dtau), so
-// the lanes of a wave read consecutive rows of one column.
+// the lanes of a wave read consecutive rows of one column, two rows per 8-byte load.
 #include "xrt_walk.h"
 
 namespace xrt {
@@ -125,10 +127,9 @@ constexpr int kWaves = kBlock / 64;
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
 template <int KB, int NR, bool ZR, bool CULL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(DevPlan P, const float* __restrict__ gT,
-                                                         float* __restrict__ img,
-                                                         const double* __restrict__ inv_v, int32_t zero_row,
-                                                         int32_t nzc, int32_t nlogical, int32_t lg_slots)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(
+    DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
+    int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots)
 {
     // per-wave records, then 1/v of every row followed by NR entries 0 for rows past
     // the detector: their z interval (0, 0) lies before tin > 0, so they are never hit
