@@ -231,6 +231,18 @@ xrt_status xrt_forward_weighted(xrt_plan* plan, const float* d_img, const float*
 xrt_status xrt_adjoint_weighted(xrt_plan* plan, const float* d_sino, const float* d_w, int32_t w_per_image,
                                 float* d_img, int32_t batch, int32_t mode, void* stream);
 
+/* Batch in the lanes (Sec. 4.3: rays independent; a batch shares every ray's walk).
+ * d_img float [n_units][batch] and d_sino float [n_rays][batch] hold 1..64 problems
+ * interleaved (unit-major; xrt_interleave converts).  One wavefront walks one ray (forward)
+ * or gathers one pixel (adjoint) for the whole batch, each lane one problem, so the
+ * batch's values of a unit or ray are one contiguous load.  Each problem's result equals
+ * that of xrt_forward / xrt_adjoint (gather) bit for bit.  The forward takes any plan;
+ * the adjoint needs a 2D plan that has the voxel-driven gather (XRT_E_UNSUPPORTED
+ * otherwise).  batch outside [1, 64]: XRT_E_ARG; batch * n_units (or n_rays) * 4 bytes
+ * beyond 31 bits: XRT_E_SIZE. */
+xrt_status xrt_forward_interleaved(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* stream);
+xrt_status xrt_adjoint_interleaved(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* stream);
+
 /* Transmission of every ray through attenuation maps: d_w[b][ray] = exp(-(A d_mu[b])[ray]),
  * the PET attenuation weight of a map given per unit length in the image layout (batch
  * maps in, batch sets of weights out).  The line integral is rounded to float32 before

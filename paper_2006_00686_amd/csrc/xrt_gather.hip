@@ -405,6 +405,93 @@ __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __r
         if (b0 + q < batch) img[(int64_t)(b0 + q) * P.n_units + pix] = (float)acc[q];
 }
 
+// 2D gather adjoint of a batch of up to 64 sinograms held interleaved ([ray][image]):
+// one lane per pixel and 8 images per lane, as k_gather2d, but a candidate's 8 values are
+// contiguous: with VEC (batch a multiple of 4) two 16-byte loads of the group's images
+// inside the batch (a group of 4 past it is not read), else 8 guarded loads.  Each
+// (pixel, image) takes the same arithmetic in the same order as k_gather2d.
+template <int MODE, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* __restrict__ sino,
+                                                         float* __restrict__ img, int32_t batch)
+{
+    constexpr int BB = 8;
+    const int32_t pix = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (pix >= P.nx * P.ny) return;
+    const int32_t b0 = blockIdx.y * BB;
+    const int32_t i = pix % P.nx, j = pix / P.nx;
+    const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
+    const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
+    const double idu = 1.0 / P.du;
+    const bool hi4 = b0 + 4 < batch;   // the group's second 4 images lie in the batch
+    double acc[BB];
+#pragma unroll
+    for (int q = 0; q < BB; ++q) acc[q] = 0.0;
+    for (int32_t v = 0; v < P.n_views; ++v) {
+        const ViewGeom& V = P.views[v];
+        const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
+        double umin = kInf, umax = -kInf;
+#pragma unroll
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const double px = ((cnr & 1) ? xb : xa) - Ax, py = ((cnr & 2) ? yb : ya) - Ay;
+            double u;
+            if constexpr (MODE == MODE_PARALLEL) {
+                u = fma(px, Bx, py * By);
+            } else if constexpr (MODE == MODE_DIVERGENT) {
+                const double e2 = Ex * Ex + Ey * Ey;
+                u = e2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+            } else {
+                u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));
+            }
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
+        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
+        for (int32_t c = c0; c <= c1; ++c) {
+            const double u = fma((double)c, P.du, P.ubase);
+            double sx, sy, dx, dy;
+            if constexpr (MODE == MODE_PARALLEL) {
+                sx = fma(u, Bx, Ax);
+                sy = fma(u, By, Ay);
+                dx = Ex;
+                dy = Ey;
+            } else if constexpr (MODE == MODE_DIVERGENT) {
+                sx = Ax;
+                sy = Ay;
+                dx = fma(u, Bx, Ex);
+                dy = fma(u, By, Ey);
+            } else {
+                const double ca = P.col_cs[2 * c], sa = P.col_cs[2 * c + 1];
+                sx = Ax;
+                sy = Ay;
+                dx = fma(ca, Ex, sa * Bx);
+                dy = fma(ca, Ey, sa * By);
+            }
+            double tin = -kInf, tout = kInf;
+            axis_interval(xa - sx, xb - sx, dx, true, tin, tout);
+            axis_interval(ya - sy, yb - sy, dy, false, tin, tout);
+            if (!(tin < tout)) continue;
+            const double len = (tout - tin) * sqrt(dx * dx + dy * dy);
+            const int64_t at = (int64_t)(v * P.n_cols + c) * batch + b0;
+            float g[BB];
+            if constexpr (VEC) {
+                const float4 lo = *reinterpret_cast<const float4*>(sino + at);
+                const float4 up = hi4 ? *reinterpret_cast<const float4*>(sino + at + 4) : make_float4(0, 0, 0, 0);
+                g[0] = lo.x; g[1] = lo.y; g[2] = lo.z; g[3] = lo.w;
+                g[4] = up.x; g[5] = up.y; g[6] = up.z; g[7] = up.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < BB; ++q) g[q] = b0 + q < batch ? sino[at + q] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < BB; ++q) acc[q] = fma((double)g[q], len, acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BB; ++q)
+        if (b0 + q < batch) img[(int64_t)pix * batch + b0 + q] = (float)acc[q];
+}
+
 template <int KB, int NR, bool CULL>
 xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t s)
 {
@@ -468,6 +555,24 @@ xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* 
             return XRT_E_UNSUPPORTED;
     }
     return hip_fail(hipGetLastError(), "2D gather launch");
+}
+
+xrt_status launch_adjoint_gather2d_il(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    const dim3 grid((unsigned)((P.nx * P.ny + kBlock - 1) / kBlock), (unsigned)((batch + 7) / 8));
+    const bool vec = (batch & 3) == 0 && ((uintptr_t)sino & 15) == 0;   // 16-byte aligned groups of 4
+    auto go = [&](auto kv, auto ks) { hipLaunchKernelGGL(vec ? kv : ks, grid, dim3(kBlock), 0, s, P, sino, img,
+                                                         (int32_t)batch); };
+    switch (P.mode) {
+        case MODE_PARALLEL: go(k_gather2d_il<MODE_PARALLEL, true>, k_gather2d_il<MODE_PARALLEL, false>); break;
+        case MODE_DIVERGENT: go(k_gather2d_il<MODE_DIVERGENT, true>, k_gather2d_il<MODE_DIVERGENT, false>); break;
+        case MODE_ARC: go(k_gather2d_il<MODE_ARC, true>, k_gather2d_il<MODE_ARC, false>); break;
+        default:
+            set_error("no gather adjoint for ray lists");
+            return XRT_E_UNSUPPORTED;
+    }
+    return hip_fail(hipGetLastError(), "interleaved 2D gather launch");
 }
 
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,

@@ -157,6 +157,10 @@ xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, floa
                                       hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
 // w[i] = exp(-x[i]) for n floats (in place allowed)
 xrt_status launch_transmission(float* w, const float* x, int64_t n, hipStream_t s);
+// batch-in-lanes forward (any 2D plan) and gather adjoint (2D gather plans): images
+// [unit][image], sinograms [ray][image], 1 <= batch <= 64
+xrt_status launch_forward_il(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s);
+xrt_status launch_adjoint_gather2d_il(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s);
 // attenuated forward reading (f, mu) pairs from p->d_att (8 n_units bytes within 32-bit
 // offsets), one image after the other
 xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride,

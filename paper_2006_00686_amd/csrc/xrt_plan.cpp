@@ -625,6 +625,34 @@ xrt_status xrt_adjoint_weighted(xrt_plan* plan, const float* d_sino, const float
                         plan != nullptr && w_per_image ? plan->dp.n_rays : 0);
 }
 
+xrt_status xrt_forward_interleaved(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 64) { set_error("interleaved batch must be in [1, 64]"); return XRT_E_ARG; }
+    if (plan->dp.n_units * batch * 4 > (int64_t)INT32_MAX - 16) {
+        set_error("interleaved images too large for 32-bit offsets");
+        return XRT_E_SIZE;
+    }
+    DeviceGuard guard(plan->device);
+    return launch_forward_il(plan, d_img, d_sino, batch, (hipStream_t)stream);
+}
+
+xrt_status xrt_adjoint_interleaved(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 64) { set_error("interleaved batch must be in [1, 64]"); return XRT_E_ARG; }
+    if (!plan->gather2d_ok) {
+        set_error("the interleaved adjoint needs a 2D scan with the image in front of every source position");
+        return XRT_E_UNSUPPORTED;
+    }
+    if (plan->dp.n_rays * batch * 4 > (int64_t)INT32_MAX - 16) {
+        set_error("interleaved sinograms too large for 32-bit offsets");
+        return XRT_E_SIZE;
+    }
+    DeviceGuard guard(plan->device);
+    return launch_adjoint_gather2d_il(plan, d_sino, d_img, batch, (hipStream_t)stream);
+}
+
 xrt_status xrt_ray_transmission(xrt_plan* plan, const float* d_mu, float* d_w, int32_t batch, void* stream)
 {
     if (!plan || !d_mu || !d_w) { set_error("null argument"); return XRT_E_ARG; }

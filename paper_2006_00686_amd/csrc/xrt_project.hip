@@ -87,6 +87,56 @@ struct FwdVisit {
     }
 };
 
+// FwdVisit for a batch in the lanes of a wavefront: every lane walks the same ray (the
+// walk's values are the same in all lanes) and reads its own image's value of each unit
+// from the interleaved layout [unit][image], so the batch's values of a unit are one
+// contiguous load.  off(I) = I * 4 batch + 4 lane.
+struct FwdBatchVisit {
+    static constexpr int32_t kIndexScale = 1;
+    __amdgpu_buffer_rsrc_t rsrc;
+    int32_t stride4, lane4;
+    double acc;
+    float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+    double q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    __device__ __forceinline__ float load(bool hit, int32_t I)
+    {
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, hit ? I * stride4 + lane4 : kOutOfRange, 0, 0));
+    }
+    __device__ __forceinline__ void consume()
+    {
+        acc = fma((double)p1, q1, acc);
+        acc = fma((double)p2, q2, acc);
+        acc = fma((double)p3, q3, acc);
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        const float f1 = load(true, I1);
+        const float f2 = load(l2 > 0.0, I2);
+        consume();
+        p1 = f1;
+        p2 = f2;
+        p3 = 0.0f;
+        q1 = l1;
+        q2 = l2;
+        q3 = 0.0;
+    }
+    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
+                                          double l3)
+    {
+        const float f1 = load(true, I1);
+        const float f2 = load(l2 > 0.0, I2);
+        const float f3 = load(l3 > 0.0, I3);
+        consume();
+        p1 = f1;
+        p2 = f2;
+        p3 = f3;
+        q1 = l1;
+        q2 = l2;
+        q3 = l3;
+    }
+};
+
 struct ScatterVisit {
     static constexpr int32_t kIndexScale = 1;
     float* img;
@@ -469,6 +519,24 @@ __global__ __launch_bounds__(kBlock) void k_forward_att(DevPlan P, const float* 
     sino[b * P.n_rays + r] = (float)v.acc;
 }
 
+// Forward projection of a batch of up to 64 images held interleaved ([unit][image]):
+// one wavefront per ray, lane = image.  Each (ray, image) takes the same arithmetic in
+// the same order as k_forward.  Lanes past the batch repeat an image and store nothing.
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forward_il(DevPlan P, const float* __restrict__ img,
+                                                        float* __restrict__ sino, int32_t batch)
+{
+    const int32_t r = (int32_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    if (r >= P.n_rays) return;
+    const int32_t lane = threadIdx.x & 63;
+    Ray R;
+    make_ray<DIM, MODE>(P, r, R);
+    FwdBatchVisit v{image_rsrc(img, (int32_t)(P.n_units * batch * 4)), 4 * batch, 4 * (lane % batch), 0.0};
+    walk<DIM>(P, R, v);
+    v.consume();
+    if (lane < batch) sino[(int64_t)r * batch + lane] = (float)(v.acc * R.scale);
+}
+
 // The attenuated forward of one image from its (f, mu) pairs.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_forward_att_pairs(DevPlan P, const float* __restrict__ pairs,
@@ -613,6 +681,7 @@ xrt_status dispatch(const DevPlan& P, dim3 grid, hipStream_t s, Args... args)
 
 template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M>; } };
 template <int D, int M> struct FwdAttK { static auto fn() { return k_forward_att<D, M>; } };
+template <int D, int M> struct FwdIlK { static auto fn() { return k_forward_il<D, M>; } };
 template <int D, int M> struct FwdAttPairK { static auto fn() { return k_forward_att_pairs<D, M>; } };
 template <int D, int M> struct AdjAttK { static auto fn() { return k_adjoint_att<D, M>; } };
 template <int D, int M> struct ScatK { static auto fn() { return k_scatter<D, M>; } };
@@ -728,6 +797,13 @@ xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* 
 {
     const DevPlan& P = p->dp;
     return dispatch<FwdAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, img, mu, mu_stride, sino);
+}
+
+xrt_status launch_forward_il(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s)
+{
+    const DevPlan& P = p->dp;
+    return dispatch<FwdIlK>(P, dim3((unsigned)((P.n_rays + kBlock / 64 - 1) / (kBlock / 64))), s, img, sino,
+                            (int32_t)batch);
 }
 
 xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride,

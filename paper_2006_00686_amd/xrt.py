@@ -87,6 +87,8 @@ def _lib():
         lib.xrt_forward_weighted.argtypes = [vp, vp, vp, i32, vp, i32, vp]
         lib.xrt_adjoint_weighted.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp]
         lib.xrt_ray_transmission.argtypes = [vp, vp, vp, i32, vp]
+        lib.xrt_forward_interleaved.argtypes = [vp, vp, vp, i32, vp]
+        lib.xrt_adjoint_interleaved.argtypes = [vp, vp, vp, i32, vp]
         lib.xrt_scan_workspace.argtypes = [i64]
         lib.xrt_scan_workspace.restype = i64
         lib.xrt_offsets_from_counts.argtypes = [i64, vp, vp, vp, vp]
@@ -306,6 +308,36 @@ class Plan:
         self._dev_check(out)
         _check(_lib().xrt_adjoint_weighted(self._h, _ptr(sino), _ptr(w), per, _ptr(out), b, ADJ[mode],
                                            _stream(self.device)), "xrt_adjoint_weighted")
+        return out
+
+    def forward_interleaved(self, img: torch.Tensor, batch: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Forward of `batch` (1..64) images held interleaved, img (n_units, batch) ->
+        (n_rays, batch) (see xrt_forward_interleaved)."""
+        self._dev_check(img)
+        if img.numel() != self.n_units * batch:
+            raise ValueError("img must hold n_units x batch floats")
+        if out is None:
+            out = torch.empty((self.n_rays, batch), dtype=torch.float32, device=img.device)
+        self._dev_check(out)
+        if out.numel() != self.n_rays * batch:
+            raise ValueError("out must hold n_rays x batch floats")
+        _check(_lib().xrt_forward_interleaved(self._h, _ptr(img), _ptr(out), batch, _stream(self.device)),
+               "xrt_forward_interleaved")
+        return out
+
+    def adjoint_interleaved(self, sino: torch.Tensor, batch: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Gather adjoint of `batch` (1..64) sinograms held interleaved, sino (n_rays, batch)
+        -> (n_units, batch); 2D plans with the voxel-driven gather."""
+        self._dev_check(sino)
+        if sino.numel() != self.n_rays * batch:
+            raise ValueError("sino must hold n_rays x batch floats")
+        if out is None:
+            out = torch.empty((self.n_units, batch), dtype=torch.float32, device=sino.device)
+        self._dev_check(out)
+        if out.numel() != self.n_units * batch:
+            raise ValueError("out must hold n_units x batch floats")
+        _check(_lib().xrt_adjoint_interleaved(self._h, _ptr(sino), _ptr(out), batch, _stream(self.device)),
+               "xrt_adjoint_interleaved")
         return out
 
     def ray_transmission(self, mu: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
