@@ -342,6 +342,15 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
             a3[st][e] = (__bf16)(m < 9 ? wload(Wc, TR, 0, m, c, 32, 1) : 0.0f);
         }
 
+    // offsets in the x ring of the C1 taps of this lane (contraction index kb * 8 + e,
+    // tap t = 3 dy + dx; indices past tap 8 read tap 8)
+    int32_t tap_off[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = min(kb * 8 + e, 8);
+        tap_off[e] = (t / 3) * kXC + t % 3;
+    }
+
     // x on the three-pixel ring of a tile (zero outside the image), three values per
     // thread, loaded into registers one tile ahead so that the global loads of the next
     // tile are in flight while this one computes
@@ -377,16 +386,21 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         __syncthreads();
         if (tile + gridDim.x < ntiles) load_ring(tile + gridDim.x);
-        // C1 on the h1 region (pixels P = 32 T + m, row P / kH1C, column P % kH1C)
+        // C1 on the h1 region (pixels P = 32 T + m, row P / kH1C, column P % kH1C).  The 8
+        // taps of a lane are read unconditionally from in-range addresses (a pixel past
+        // the region reads pixel 0, a contraction index past the 9 taps reads tap 8) and
+        // the unused ones are zeroed afterwards, so the reads are issued together
         for (int T = wv; T < kH1Tiles; T += kPB / 64) {
-            const int32_t P = T * 32 + m, pr = P / kH1C, pc = P % kH1C;
+            const int32_t P = T * 32 + m;
             const bool valid = P < kH1N;
+            const int32_t Pc = valid ? P : 0, pr = Pc / kH1C, pc = Pc - pr * kH1C;
+            const float* const xp = &sx[pr * kXC + pc];
+            float xv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xv[e] = xp[tap_off[e]];
             bf16x8 bx;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int t = kb * 8 + e;
-                bx[e] = (__bf16)((valid && t < 9) ? sx[(pr + t / 3) * kXC + pc + t % 3] : 0.0f);
-            }
+            for (int e = 0; e < 8; ++e) bx[e] = (__bf16)(valid && kb * 8 + e < 9 ? xv[e] : 0.0f);
             const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bx, f32x16{}, 0, 0, 0);
             if (valid) {
                 const int32_t iy = Y0 - 2 + pr, ix = X0 - 2 + pc;
