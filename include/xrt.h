@@ -27,7 +27,12 @@
  *   marked d_, host pointers otherwise).  A plan owns its device tables; destroy frees
  *   them.  Host arrays referenced by xrt_scan are copied during xrt_plan_create.
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
- *   asynchronously; no call below synchronises the host except plan create/destroy.
+ *   asynchronously; no call below synchronises the host except plan create/destroy and
+ *   the first xrt_forward_attenuated on a plan (it allocates that plan's workspace).
+ * Concurrency: a plan's device workspaces (the cone gather's transposed sinogram, the
+ *   forward's y-fastest copy, the attenuated forward's pairs) are shared by its calls, so
+ *   calls on one plan must be ordered: one stream, or events between streams.  Different
+ *   plans are independent.
  * Errors: every call returns an xrt_status.  Arguments are validated before any work
  *   is enqueued, so a failed call writes nothing.  XRT_E_HIP carries the HIP runtime
  *   message in xrt_last_error() (per thread).
