@@ -379,6 +379,8 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
         const uint32_t bi = rest / tiles_y;
         const int32_t Y0 = (int32_t)(rest - bi * tiles_y) * kTH;
         const int64_t img = (int64_t)bi * H * Wd;
+        // the tile's x ring (3 pixels around it) lies inside the image: no edge masks
+        const bool interior = X0 >= 3 && Y0 >= 3 && X0 + kTW + 3 <= Wd && Y0 + kTH + 3 <= H;
 #pragma unroll
         for (int j = 0; j < kXPer; ++j) {
             const int k = threadIdx.x + j * kPB;
@@ -403,14 +405,24 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int e = 0; e < 8; ++e) bx[e] = (__bf16)(valid && kb * 8 + e < 9 ? xv[e] : 0.0f);
             const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bx, f32x16{}, 0, 0, 0);
             if (valid) {
-                const int32_t iy = Y0 - 2 + pr, ix = X0 - 2 + pc;
-                const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+                // channels 8 g + 4 kb .. + 3 of pixel P (h1 is zero outside the image;
+                // a tile whose x ring lies inside the image needs no mask)
+                if (interior) {
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    // channels 8 g + 4 kb .. + 3 of pixel P
-                    __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
+                    for (int g = 0; g < 4; ++g) {
+                        __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) dst[q] = (__bf16)(in ? d[4 * g + q] : 0.0f);
+                        for (int q = 0; q < 4; ++q) dst[q] = (__bf16)d[4 * g + q];
+                    }
+                } else {
+                    const int32_t iy = Y0 - 2 + pr, ix = X0 - 2 + pc;
+                    const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[q] = (__bf16)(in ? d[4 * g + q] : 0.0f);
+                    }
                 }
             }
         }
@@ -435,13 +447,21 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int32_t R = wv + 4 * j;
-            const int32_t iy = Y0 - 1 + R, ix = X0 - 1 + m;
-            const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
             bf16x8 b0, b1;
+            if (interior) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                b0[e] = (__bf16)(in ? h2[j][e] : 0.0f);
-                b1[e] = (__bf16)(in ? h2[j][8 + e] : 0.0f);
+                for (int e = 0; e < 8; ++e) {
+                    b0[e] = (__bf16)h2[j][e];
+                    b1[e] = (__bf16)h2[j][8 + e];
+                }
+            } else {
+                const int32_t iy = Y0 - 1 + R, ix = X0 - 1 + m;
+                const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    b0[e] = (__bf16)(in ? h2[j][e] : 0.0f);
+                    b1[e] = (__bf16)(in ? h2[j][8 + e] : 0.0f);
+                }
             }
             f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b0, f32x16{}, 0, 0, 0);
             u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b1, u, 0, 0, 0);
