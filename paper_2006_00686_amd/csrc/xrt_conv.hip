@@ -310,7 +310,7 @@ constexpr int kH1Tiles = (kH1N + 31) / 32;          // 20
 constexpr int kH1S = 40;                            // LDS stride of an h1 pixel (bf16; 80 B)
 constexpr int kPB = 256;
 static_assert(kH2C == 32 && kH2R == 4 * (kPB / 64), "one 32-pixel row per MFMA tile, four per wave");
-static_assert(9 * kH2R * kH2C * 4 <= kH1N * kH1S * 2, "tap partials fit in the h1 buffer");
+
 
 template <bool TR>
 __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k_precond(const float* __restrict__ x, const float* __restrict__ Wa,
@@ -318,9 +318,13 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                   float* __restrict__ y, int32_t H, int32_t Wd, uint32_t tiles_x,
                                                   uint32_t tiles_y, uint32_t ntiles)
 {
-    __shared__ float sx[kXR * kXC];   // x on the ring (FP32: also the residual)
+    // x on the ring (FP32: also the residual), double-buffered: a tile's ring is stored
+    // while other waves may still read the previous tile's; the tap partials have their
+    // own buffer, so C3 need not wait for every wave's C2 reads of h1 (three barriers per
+    // tile)
+    __shared__ float sx2[2][kXR * kXC];
     __shared__ __attribute__((aligned(16))) __bf16 sh1[kH1N * kH1S];
-    float* su = (float*)sh1;   // tap partials [9][kH2R][kH2C], after C2 has read h1
+    __shared__ float su[9 * kH2R * kH2C];   // tap partials [9][kH2R][kH2C]
 
     const int32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = lane & 31, kb = lane >> 5;
     // weights as MFMA A operands (row m of lane l = l % 32, contraction index kb * 8 + e)
@@ -373,7 +377,9 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     };
     if (blockIdx.x < ntiles) load_ring(blockIdx.x);
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    uint32_t parity = 0;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
+        float* const sx = sx2[parity];
         const uint32_t rest = tile / tiles_x;
         const int32_t X0 = (int32_t)(tile - rest * tiles_x) * kTW;
         const uint32_t bi = rest / tiles_y;
@@ -442,7 +448,6 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int j = 0; j < 4; ++j) h2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[st], b[j], h2[j], 0, 0, 0);
         }
-        __syncthreads();
         // C3 tap partials into LDS (h2 zero outside the image)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -480,7 +485,6 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
                 y[img + (int64_t)iy * Wd + ix] = sx[(r + 3) * kXC + c + 3] + sum;
             }
         }
-        __syncthreads();
     }
 }
 
