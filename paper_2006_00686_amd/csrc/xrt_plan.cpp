@@ -546,8 +546,15 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
     const int64_t mu_stride = mu_per_image ? plan->dp.n_units : 0;
     // (f, mu) interleaved, so that each candidate takes one 8-byte load; the pairs of
     // one image live in a plan workspace allocated here on first use
+    // (never during stream capture: a captured call without the workspace takes the
+    // unpaired walk and allocates nothing)
     if (plan->dp.n_units * 8 <= (int64_t)INT32_MAX - 16) {
-        if (plan->d_att == nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (plan->d_att == nullptr && hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            cs = hipStreamCaptureStatusActive;
+        }
+        if (plan->d_att == nullptr && cs == hipStreamCaptureStatusNone) {
             void* ws = nullptr;
             if (hipMalloc(&ws, (size_t)plan->dp.n_units * 2 * sizeof(float)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -557,7 +564,8 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
             }
             plan->d_att = (float*)ws;
         }
-        return launch_forward_att_pairs(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
+        if (plan->d_att != nullptr)
+            return launch_forward_att_pairs(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
     }
     return launch_forward_att(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
 }

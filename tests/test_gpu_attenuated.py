@@ -103,3 +103,25 @@ def test_cone_256_attenuated_sampled(X):
     scl = ocore.forward_att_lines(cfg["grid"], p[pick], th[pick], np.abs(img).astype(np.float64),
                                   mu.astype(np.float64))
     H.assert_within_bar(got[gidx], ref, scl, what="cone_256 attenuated sampled")
+
+
+def test_attenuated_forward_captured_before_its_workspace(X):
+    """A captured call on a plan without the pair workspace allocates nothing and takes the
+    unpaired walk; replays equal the paired eager result bit for bit."""
+    grid, scan = _scan("cone_flat")
+    plan = X.Plan(grid, scan)
+    rng = np.random.default_rng(71)
+    img = torch.from_numpy(inputs.random_image(inputs.image_shape(grid), 72)).to(DEV)
+    mu = torch.from_numpy(rng.uniform(0, 0.2, inputs.image_shape(grid)).astype(np.float32)).to(DEV)
+    out = torch.empty(tuple(plan.sino_shape), device=DEV)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.forward_attenuated(img, mu, out=out)
+    eager = plan.forward_attenuated(img, mu)   # allocates the workspace: paired walk
+    for _ in range(3):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
+        _ = plan.forward(img)   # eager work between replays
