@@ -53,6 +53,25 @@ def measured_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def copy_bandwidth(dev, stream, mib: int = 1024, reps: int = 10) -> float:
+    """Measured device-to-device copy rate (bytes read + written per second, GB/s) of a
+    `mib` MiB buffer: the practical ceiling the datasheet HBM peak is compared with."""
+    import torch
+    src = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * mib * (1 << 20) / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def cpu_baseline(cfg, img, views_every: int):
     """The FP64 oracle, as it stands, on every `views_every`-th view of the scan."""
     from oracle import core as ocore
@@ -170,7 +189,7 @@ def batched_bench(torch, dev, steps: int, tuning: dict):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--adjoint", default="auto", choices=["auto", "scatter", "gather"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -236,8 +255,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    t_fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    t_adj = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    # per-kernel times: median over the timed steps (robust to a stray slow step)
+    t_fwd = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+    t_adj = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
     log(f"[bench] {ms_step:.3f} ms/step (events: forward {t_fwd:.3f} ms, adjoint {t_adj:.3f} ms)")
 
     b_fwd = 4.0 * nnz + 4.0 * M        # one 4-byte gather per hit + the ray's output
@@ -249,11 +269,14 @@ def main():
         kname, bytes_, t_k = adj_kernel, b_adj, t_adj
     achieved = bytes_ / (t_k * 1e-3) / 1e9
     traffic = measured_traffic(kname)
+    copy_gbs = copy_bandwidth(dev, stream)
+    log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s (read + write)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "kernel_ms": round(t_k, 4), "algorithmic_bytes": bytes_,
                 "fwd_ms": round(t_fwd, 4), "adj_ms": round(t_adj, 4),
-                "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     # the attenuated transform (SPECT weight) of the same workload, mu = 0.01 per unit length
     log("[bench] attenuated transform")
