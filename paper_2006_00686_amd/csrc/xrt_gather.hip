@@ -115,6 +115,7 @@ constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
 struct ColRecs {
     double tin[64], tout[64], sin[64], sout[64], sz[64];
     int32_t g[64];
+    int32_t klo[64], khi[64];   // helical scans: voxel indices k the record's rays can reach
 };
 constexpr int kWaves = kBlock / 64;
 
@@ -126,10 +127,12 @@ constexpr int kWaves = kBlock / 64;
 // rows are exactly the ones that would add nothing.
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
+// vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling; kernel
+// arguments, so they stay in scalar registers).
 template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(
     DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
-    int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots)
+    int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz)
 {
     // per-wave records, then 1/v of every row followed by NR entries 0 for rows past
     // the detector: their z interval (0, 0) lies before tin > 0, so they are never hit
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
     const double vb = -P.vbase * idv;
-    const int32_t kbase = zc * 64 * KB + lane;
+    const int32_t kfirst = zc * 64 * KB, kbase = kfirst + lane;
     const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, (P.n_rays + kGatherPad) * 4);
 
     double acc[KB], zb0[KB];
@@ -212,6 +215,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 R.sout[at] = rcp_fast(tout) * idv;
                 R.sz[at] = V.A[2];
                 R.g[at] = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
+                if constexpr (CULL && KB == 4) {
+                    // heights z = Sz + tau v over tau in (tin, tout) and v in [vmin, vmax]
+                    // (bilinear: extremes at the corners), widened by a hundredth of a
+                    // unit; voxel k spans z in (pz0 - (k + 1) dz, pz0 - k dz]
+                    const double zlo = V.A[2] + fmin(tin * vmin, tout * vmin) - 0.01 * P.pdz;
+                    const double zhi = V.A[2] + fmax(tin * vmax, tout * vmax) + 0.01 * P.pdz;
+                    R.klo[at] = (int32_t)floor(fmin(fmax((P.pz0 - zhi) * idz, -2.0), (double)P.nz + 1.0));
+                    R.khi[at] = (int32_t)floor(fmin(fmax((P.pz0 - zlo) * idz, -2.0), (double)P.nz + 1.0));
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -292,14 +304,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     }
                 };
                 if constexpr (CULL) {
-                    // helical scans: most voxels of a record are culled, so each is done
-                    // in full where it is not
+                    // helical scans: most voxels of a record are culled, first a block of 64
+                    // that the record's rays cannot reach (scalar test), then by the vote in
+                    // head(); a block that remains is done in full
+                    // (with 4 voxels per lane; shorter chunks rely on the vote alone)
+                    const int32_t klo = KB == 4 ? __builtin_amdgcn_readfirstlane(R.klo[e]) : -2;
+                    const int32_t khi = KB == 4 ? __builtin_amdgcn_readfirstlane(R.khi[e]) : P.nz + 1;
 #pragma unroll
-                    for (int q = 0; q < KB; ++q)
-                        if (head(q)) {
+                    for (int q = 0; q < KB; ++q) {
+                        const int32_t k0 = kfirst + 64 * q;
+                        if (khi >= k0 && klo <= k0 + 63 && head(q)) {
                             body(q);
                             tail(q);
                         }
+                    }
                 } else {
                     // the loads of every voxel of the lane in flight together
 #pragma unroll
@@ -505,12 +523,16 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
     }
     const int64_t launched = (nlog + 7) / 8 * 8;
     const size_t lds = kWaves * sizeof(ColRecs) + (size_t)(P.n_rows + NR) * sizeof(double);
+    const double vlast = P.vbase + (P.n_rows - 1) * P.dv;
+    const double vmin = std::fmin(P.vbase, vlast), vmax = std::fmax(P.vbase, vlast);
     if (p->zero_row >= 0)
         hipLaunchKernelGGL((k_cone_gather<KB, NR, true, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
-                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs);
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
+                           vmin, vmax, 1.0 / P.pdz);
     else
         hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
-                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs);
+                           gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
+                           vmin, vmax, 1.0 / P.pdz);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 
