@@ -269,14 +269,17 @@ def main():
         kname, bytes_, t_k = adj_kernel, b_adj, t_adj
     achieved = bytes_ / (t_k * 1e-3) / 1e9
     traffic = measured_traffic(kname)
-    copy_gbs = copy_bandwidth(dev, stream)
-    log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s (read + write)")
+    # (not in counter runs, whose only large copy must be the 256 MiB reference)
+    copy_gbs = None if args.copy_reference else copy_bandwidth(dev, stream)
+    if copy_gbs:
+        log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s (read + write)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "kernel_ms": round(t_k, 4), "algorithmic_bytes": bytes_,
                 "fwd_ms": round(t_fwd, 4), "adj_ms": round(t_adj, 4),
                 "fwd_plus_adj_frac": round((b_fwd + b_adj) / ((t_fwd + t_adj) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+                "copy_GBps": round(copy_gbs, 1) if copy_gbs else None,
+                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
 
     # the attenuated transform (SPECT weight) of the same workload, mu = 0.01 per unit length
     log("[bench] attenuated transform")

@@ -51,6 +51,10 @@ def build(fetch_db: str, write_db: str) -> dict:
     fetch, write = _averages(fetch_db, "FETCH_SIZE"), _averages(write_db, "WRITE_SIZE")
     if "copy" not in fetch or "copy" not in write:
         raise SystemExit("no copy-reference dispatch in the counter runs (bench.py --copy-reference)")
+    # the reference writes exactly its 256 MiB: another large copy in the run would be
+    # taken for it and scale every figure wrongly
+    if abs(write["copy"] * 1024.0 - COPY_BYTES) > 0.01 * COPY_BYTES:
+        raise SystemExit(f"largest copy wrote {write['copy']:.0f} KiB, not the 256 MiB reference")
     fs = COPY_BYTES / 1024.0 / fetch["copy"]
     ws = COPY_BYTES / 1024.0 / write["copy"]
     kernels = {}

@@ -43,3 +43,12 @@ def test_missing_reference_copy_is_an_error(tmp_path):
     _db(write, "WRITE_SIZE", [("k_forward<3, 1>", 1.0)])
     with pytest.raises(SystemExit):
         traffic.build(fetch, write)
+
+
+def test_a_copy_other_than_the_reference_is_rejected(tmp_path):
+    fetch, write = str(tmp_path / "f.db"), str(tmp_path / "w.db")
+    fwd = "void xrt::(anonymous namespace)::k_forward<3, 1>(xrt::DevPlan)"
+    _db(fetch, "FETCH_SIZE", [(fwd, 1.0), ("__amd_rocclr_copyBuffer", 524288.0)])
+    _db(write, "WRITE_SIZE", [(fwd, 1.0), ("__amd_rocclr_copyBuffer", 1048576.0)])   # a 1 GiB copy
+    with pytest.raises(SystemExit):
+        traffic.build(fetch, write)
