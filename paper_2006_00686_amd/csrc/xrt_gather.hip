@@ -134,11 +134,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
     int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz)
 {
-    // per-wave records, then 1/v of every row followed by NR entries 0 for rows past
-    // the detector: their z interval (0, 0) lies before tin > 0, so they are never hit
+    // 1/v of every row followed by NR entries 0 for rows past the detector (their z
+    // interval (0, 0) lies before tin > 0, so they are never hit), then the per-wave
+    // records; the table comes first so that its addresses need no base
     extern __shared__ double s_dyn[];
-    ColRecs* const s_rec = reinterpret_cast<ColRecs*>(s_dyn);
-    double* const s_iv = s_dyn + kWaves * sizeof(ColRecs) / sizeof(double);
+    double* const s_iv = s_dyn;
+    ColRecs* const s_rec = reinterpret_cast<ColRecs*>(s_dyn + ((P.n_rows + NR + 1) & ~1));
     for (int32_t r = threadIdx.x; r < P.n_rows + NR; r += kBlock) s_iv[r] = r < P.n_rows ? inv_v[r] : 0.0;
     __syncthreads();
 
@@ -161,6 +162,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
     const double vb = -P.vbase * idv;
+    // candidate rows are widened by kRangeSlack bins on both sides
+    const double vb_lo = vb - kRangeSlack, vb_hi = vb + kRangeSlack;
     const int32_t kfirst = zc * 64 * KB, kbase = kfirst + lane;
     const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, (P.n_rays + kGatherPad) * 4);
 
@@ -258,18 +261,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     // first candidate row: the smallest v = rel / tau of the voxel over
                     // tau in (tin, tout), in bin units
                     const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
-                    const double vlo = fmin(fma(rel0, sin_, vb), fma(rel0, sout, vb));
+                    const double vlo = fmin(fma(rel0, sin_, vb_lo), fma(rel0, sout, vb_lo));
                     // rows outside the voxel's range fail C_low < C_up below on their own
                     // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
-                    r0[q] = min(max((int32_t)ceil(vlo - kRangeSlack), 0), P.n_rows);
-                    const double vhi = fmax(fma(rel1, sin_, vb), fma(rel1, sout, vb));
-                    more[q] = NR > 2 && vhi + kRangeSlack >= (double)(r0[q] + 2);
+                    r0[q] = min(max((int32_t)ceil(vlo), 0), P.n_rows);
+                    const double vhi = fmax(fma(rel1, sin_, vb_hi), fma(rel1, sout, vb_hi));
+                    more[q] = NR > 2 && vhi >= (double)(r0[q] + 2);
                     if constexpr (CULL) {
                         // rows past the detector are zero padding; a voxel whose rows all
                         // lie above the first row (by half a bin, far beyond the error of
                         // the estimates) has no hit in rows r0 = 0 ..
                         const int32_t k = kbase + 64 * q;
-                        const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5;
+                        const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5 + kRangeSlack;
                         if (__builtin_amdgcn_ballot_w64(any) == 0) return false;
                     }
                     l0[q] = len(r0[q], rel0, rel1);
@@ -522,7 +525,7 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
         return XRT_E_SIZE;
     }
     const int64_t launched = (nlog + 7) / 8 * 8;
-    const size_t lds = kWaves * sizeof(ColRecs) + (size_t)(P.n_rows + NR) * sizeof(double);
+    const size_t lds = kWaves * sizeof(ColRecs) + (size_t)((P.n_rows + NR + 1) & ~1) * sizeof(double);
     const double vlast = P.vbase + (P.n_rows - 1) * P.dv;
     const double vmin = std::fmin(P.vbase, vlast), vmax = std::fmax(P.vbase, vlast);
     if (p->zero_row >= 0)
