@@ -295,19 +295,36 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
             const double e2 = dt2 - dt0;
             double r2 = fmax(tn2 - tx0, 0.0);
             const double r2s = r2;
+            int32_t s = nint;
+            while (s > 0) {
+                // slabs in which the ray crosses no plane of the second secondary axis
+                // (r2 >= dt0): the candidates and lengths of the general slab below
+                // reduce to those of a 2D slab (its third length is dt0 - r2 <= 0)
 #pragma unroll 2
-            for (int32_t s = nint; s > 0; --s) {
-                const double a = fmin(r1, r2), b = fmax(r1, r2);
-                const double l1 = fmin(a, dt0);
-                const double l2 = fmin(b, dt0) - a;
-                const double l3 = dt0 - b;
-                const bool c1 = r1 < dt0, c2 = r2 < dt0;
-                const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
-                const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
-                vis.three(I, l1, Imid, l2, Iend, l3);
-                r1 += c1 ? e1 : -dt0;
-                r2 += c2 ? e2 : -dt0;
-                I = Iend + sd0;
+                for (; s > 0 && r2 >= dt0; --s) {
+                    const double l1 = fmin(r1, dt0);
+                    const double l2 = dt0 - r1;
+                    const bool c1 = r1 < dt0;
+                    const int32_t Iend = c1 ? I + sd1 : I;
+                    vis.two(I, l1, Iend, l2);
+                    r1 += c1 ? e1 : -dt0;
+                    r2 -= dt0;
+                    I = Iend + sd0;
+                }
+                if (s > 0) {
+                    const double a = fmin(r1, r2), b = fmax(r1, r2);
+                    const double l1 = fmin(a, dt0);
+                    const double l2 = fmin(b, dt0) - a;
+                    const double l3 = dt0 - b;
+                    const bool c1 = r1 < dt0, c2 = r2 < dt0;
+                    const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
+                    const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
+                    vis.three(I, l1, Imid, l2, Iend, l3);
+                    r1 += c1 ? e1 : -dt0;
+                    r2 += c2 ? e2 : -dt0;
+                    I = Iend + sd0;
+                    --s;
+                }
             }
             // crossings taken along the second secondary axis (see n1 below)
             const int32_t n2 = (int32_t)rint((r2 - r2s + (double)nint * dt0) / dt2);
