@@ -127,12 +127,14 @@ constexpr int kWaves = kBlock / 64;
 // rows are exactly the ones that would add nothing.
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
-// vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling; kernel
-// arguments, so they stay in scalar registers).
+// vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling); vb_lo,
+// vb_hi: row coordinate of v = 0 in bins, -vbase / dv, minus and plus the candidate
+// rows' slack of kRangeSlack bins (kernel arguments, so they stay in scalar registers).
 template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(
     DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
-    int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz)
+    int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz,
+    double vb_lo, double vb_hi)
 {
     // 1/v of every row followed by NR entries 0 for rows past the detector (their z
     // interval (0, 0) lies before tin > 0, so they are never hit), then the per-wave
@@ -161,9 +163,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double sdd2 = P.sdd * P.sdd, idu = 1.0 / P.du, idv = 1.0 / P.dv;
-    const double vb = -P.vbase * idv;
-    // candidate rows are widened by kRangeSlack bins on both sides
-    const double vb_lo = vb - kRangeSlack, vb_hi = vb + kRangeSlack;
+
     const int32_t kfirst = zc * 64 * KB, kbase = kfirst + lane;
     const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, (P.n_rays + kGatherPad) * 4);
 
@@ -528,14 +528,15 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
     const size_t lds = kWaves * sizeof(ColRecs) + (size_t)((P.n_rows + NR + 1) & ~1) * sizeof(double);
     const double vlast = P.vbase + (P.n_rows - 1) * P.dv;
     const double vmin = std::fmin(P.vbase, vlast), vmax = std::fmax(P.vbase, vlast);
+    const double vb = -P.vbase * (1.0 / P.dv);
     if (p->zero_row >= 0)
         hipLaunchKernelGGL((k_cone_gather<KB, NR, true, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack);
     else
         hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 

@@ -406,7 +406,7 @@ __host__ __device__ inline uint64_t forward_threads(const DevPlan& P)
 // or NULL; a wavefront reads it when the detector u axis of its view runs closer to y
 // than to x: its lanes then step along y, and the transposed layout keeps their gathers
 // in consecutive addresses.
-template <int DIM, int MODE>
+template <int DIM, int MODE, bool NEST = false>
 __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const float* img, const float* imgT,
                                             float* sino, const float* wt = nullptr)
 {
@@ -426,7 +426,7 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
         }
     }
     FwdVisit v{image_rsrc(base, (int32_t)(P.n_units * 4)), 0.0};
-    walk<DIM>(P, R, v);
+    walk<DIM, NEST>(P, R, v);
     v.consume();
     // wt: a per-ray weight (the PET form of the generalised transform), or none
     const double w = wt != nullptr ? (double)wt[r] : 1.0;
@@ -435,7 +435,7 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
 
 // nblocks: workgroups that carry rays; with xcd_remap the grid is rounded up to a
 // multiple of 8 and workgroup b takes logical block (b % 8) * (grid / 8) + b / 8.
-template <int DIM, int MODE>
+template <int DIM, int MODE, bool NEST>
 __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
                                                      const float* __restrict__ imgT, float* __restrict__ sino,
                                                      uint32_t nblocks, const float* __restrict__ wt,
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __re
     const int32_t r = forward_ray_of<MODE>(P, (uint64_t)blk * kBlock + threadIdx.x);
     if (r < 0) return;
     const int64_t b = blockIdx.y;
-    forward_one<DIM, MODE>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays,
+    forward_one<DIM, MODE, NEST>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays,
                            wt != nullptr ? wt + b * wt_stride : nullptr);
 }
 
@@ -679,7 +679,8 @@ xrt_status dispatch(const DevPlan& P, dim3 grid, hipStream_t s, Args... args)
     }
 }
 
-template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M>; } };
+template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M, false>; } };
+template <int D, int M> struct FwdNestK { static auto fn() { return k_forward<D, M, D == 3>; } };
 template <int D, int M> struct FwdAttK { static auto fn() { return k_forward_att<D, M>; } };
 template <int D, int M> struct FwdIlK { static auto fn() { return k_forward_il<D, M>; } };
 template <int D, int M> struct FwdAttPairK { static auto fn() { return k_forward_att_pairs<D, M>; } };
@@ -717,15 +718,20 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
     if (nb64 > 0x7FFFFFF0ull) { set_error("forward launch too large"); return XRT_E_SIZE; }
     const uint32_t nb = (uint32_t)nb64;
     const uint32_t grid = P.xcd_remap ? (nb + 7u) / 8u * 8u : nb;
+    // the walk's form (see walk()): chosen per plan
+    auto launch = [&](dim3 g, const float* im, const float* imT, float* sn, const float* w,
+                      int64_t ws) -> xrt_status {
+        return P.nest_z ? dispatch<FwdNestK>(P, g, s, im, imT, sn, nb, w, ws)
+                        : dispatch<FwdK>(P, g, s, im, imT, sn, nb, w, ws);
+    };
     if (p->d_imgT == nullptr)
-        return dispatch<FwdK>(P, dim3(grid, (unsigned)batch), s, img, (const float*)nullptr, sino, nb, wt,
-                              wt_stride);
+        return launch(dim3(grid, (unsigned)batch), img, (const float*)nullptr, sino, wt, wt_stride);
     for (int b = 0; b < batch; ++b) {
         const float* im = img + (int64_t)b * P.n_units;
         xrt_status st = launch_transpose_xy(P, im, p->d_imgT, s);
         if (st != XRT_OK) return st;
-        st = dispatch<FwdK>(P, dim3(grid, 1u), s, im, (const float*)p->d_imgT, sino + (int64_t)b * P.n_rays, nb,
-                            wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr, (int64_t)0);
+        st = launch(dim3(grid, 1u), im, (const float*)p->d_imgT, sino + (int64_t)b * P.n_rays,
+                    wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr, (int64_t)0);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;

@@ -202,7 +202,13 @@ XRT_HD bool setup_axes(const DevPlan& P, const Ray& R, Axis* ax,
 // axis, the distance r from the slab start to the next crossing and step it by the slab
 // width dt0 (a DDA in the ray parameter): two fewer exact evaluations per slab and no
 // bounds logic, which the one-slab margin to the chord's end makes unnecessary.
-template <int DIM, class Visit>
+//
+// NEST (3D): the interior slabs in which the ray crosses no plane of the second secondary
+// axis take a cheaper 2D form in an inner loop (same candidates, lengths and order of the
+// visits).  Lanes of a wavefront then wait for each other at those crossings, which pays
+// where the lanes' crossings fall in nearly the same slabs (coarse grids seen from far
+// away); the flat form is the default.
+template <int DIM, bool NEST = false, class Visit>
 XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
 {
     constexpr double kNone = 1e300;   // "no further crossing" (finite: 0 * l stays 0)
@@ -295,23 +301,9 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
             const double e2 = dt2 - dt0;
             double r2 = fmax(tn2 - tx0, 0.0);
             const double r2s = r2;
-            int32_t s = nint;
-            while (s > 0) {
-                // slabs in which the ray crosses no plane of the second secondary axis
-                // (r2 >= dt0): the candidates and lengths of the general slab below
-                // reduce to those of a 2D slab (its third length is dt0 - r2 <= 0)
+            if constexpr (!NEST) {
 #pragma unroll 2
-                for (; s > 0 && r2 >= dt0; --s) {
-                    const double l1 = fmin(r1, dt0);
-                    const double l2 = dt0 - r1;
-                    const bool c1 = r1 < dt0;
-                    const int32_t Iend = c1 ? I + sd1 : I;
-                    vis.two(I, l1, Iend, l2);
-                    r1 += c1 ? e1 : -dt0;
-                    r2 -= dt0;
-                    I = Iend + sd0;
-                }
-                if (s > 0) {
+                for (int32_t s = nint; s > 0; --s) {
                     const double a = fmin(r1, r2), b = fmax(r1, r2);
                     const double l1 = fmin(a, dt0);
                     const double l2 = fmin(b, dt0) - a;
@@ -323,7 +315,38 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                     r1 += c1 ? e1 : -dt0;
                     r2 += c2 ? e2 : -dt0;
                     I = Iend + sd0;
-                    --s;
+                }
+            } else {
+                int32_t s = nint;
+                while (s > 0) {
+                    // slabs in which the ray crosses no plane of the second secondary axis
+                    // (r2 >= dt0): the candidates and lengths of the general slab below
+                    // reduce to those of a 2D slab (its third length is dt0 - r2 <= 0)
+#pragma unroll 2
+                    for (; s > 0 && r2 >= dt0; --s) {
+                        const double l1 = fmin(r1, dt0);
+                        const double l2 = dt0 - r1;
+                        const bool c1 = r1 < dt0;
+                        const int32_t Iend = c1 ? I + sd1 : I;
+                        vis.two(I, l1, Iend, l2);
+                        r1 += c1 ? e1 : -dt0;
+                        r2 -= dt0;
+                        I = Iend + sd0;
+                    }
+                    if (s > 0) {
+                        const double a = fmin(r1, r2), b = fmax(r1, r2);
+                        const double l1 = fmin(a, dt0);
+                        const double l2 = fmin(b, dt0) - a;
+                        const double l3 = dt0 - b;
+                        const bool c1 = r1 < dt0, c2 = r2 < dt0;
+                        const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
+                        const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
+                        vis.three(I, l1, Imid, l2, Iend, l3);
+                        r1 += c1 ? e1 : -dt0;
+                        r2 += c2 ? e2 : -dt0;
+                        I = Iend + sd0;
+                        --s;
+                    }
                 }
             }
             // crossings taken along the second secondary axis (see n1 below)

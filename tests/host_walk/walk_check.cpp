@@ -1,6 +1,7 @@
 // Host build of the GPU path's ray construction and slab walk (xrt_walk.h), run on the
 // CPU over whole scans.  For every ray it records the hit list and checks that every
-// image index the forward kernel would dereference lies inside the image.
+// image index the forward kernel would dereference lies inside the image, and (3D) that
+// the walk's nested form gives the same hit list bit for bit.
 //
 // usage: walk_check <scan.txt> <hits.bin>
 // scan.txt: "kind nx ny nz dx dy dz cx cy cz" / "n_views n_rows n_cols du dv u0 v0 sod sdd
@@ -64,6 +65,13 @@ long run(const DevPlan& P, double eps, FILE* out)
         CheckVisit v{P.n_units, eps / R.scale, R.scale, {}, {}, 0};
         walk<DIM>(P, R, v);
         bad += v.bad;
+        if constexpr (DIM == 3) {
+            // the nested form of the walk visits the same hits with the same lengths
+            CheckVisit vn{P.n_units, eps / R.scale, R.scale, {}, {}, 0};
+            walk<DIM, true>(P, R, vn);
+            bad += vn.bad;
+            if (vn.idx != v.idx || vn.len != v.len) ++bad;
+        }
         int32_t n = (int32_t)v.idx.size();
         fwrite(&n, 4, 1, out);
         for (int32_t k = 0; k < n; ++k) {
