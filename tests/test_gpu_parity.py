@@ -129,6 +129,28 @@ def test_forward_parity(xrt, name, grid, scan):
     assert np.all(got.ravel()[scl == 0] == 0)
 
 
+# Grids wider than 256 units take the flat form of the 3D walk in the forward projection;
+# the small scans above (all narrower) take its nested form.
+WIDE_SCANS = [
+    ("cone_flat_wide", dict(nx=300, ny=262, nz=6, dx=1.0, dy=1.0, dz=1.0, cx=0.5, cy=-0.5, cz=0.0),
+     dict(kind="cone_flat", angles=np.linspace(0.05, 2 * PI, 6, endpoint=False), ncols=70, nrows=9, du=5.0,
+          dv=1.0, sod=400.0, sdd=600.0)),
+    ("par3d_wide", dict(nx=270, ny=290, nz=5, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0),
+     dict(kind="par3d", angles=np.linspace(0.1, PI, 5, endpoint=False), phi2=np.linspace(-0.02, 0.02, 5),
+          ncols=67, nrows=7, du=4.3, dv=0.7)),
+]
+
+
+@pytest.mark.parametrize("name,grid,scan", WIDE_SCANS, ids=[s[0] for s in WIDE_SCANS])
+def test_forward_parity_wide_grid(xrt, name, grid, scan):
+    img = inputs.random_image(inputs.image_shape(grid), 37)
+    plan = xrt.Plan(grid, scan)
+    got = plan.forward(torch.from_numpy(img).to(dev())).cpu().numpy()
+    ref, scl = H.forward_bar(grid, scan, img)
+    assert np.count_nonzero(scl) > 0.8 * scl.size
+    H.assert_within_bar(got, ref, scl, what=f"forward {name}")
+
+
 @pytest.mark.parametrize("name,grid,scan", SCANS, ids=[s[0] for s in SCANS])
 def test_adjoint_scatter_parity(xrt, name, grid, scan):
     rng = np.random.default_rng(5)
