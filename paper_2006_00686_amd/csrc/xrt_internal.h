@@ -55,8 +55,8 @@ struct DevPlan {
     // contiguous range of packets (workgroups are dealt to the 8 XCDs round robin)
     int32_t packet_cols = 0;
     int32_t xcd_remap = 0;
-    // 3D forward projection: walk form (0 flat, 1 nested; no effect on results), set at
-    // plan creation
+    // 3D forward projections (plain and attenuated): walk form (0 flat, 1 nested; no
+    // effect on results), set at plan creation
     int32_t nest_z = 0;
 };
 

@@ -537,8 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_il(DevPlan P, const float* _
     if (lane < batch) sino[(int64_t)r * batch + lane] = (float)(v.acc * R.scale);
 }
 
-// The attenuated forward of one image from its (f, mu) pairs.
-template <int DIM, int MODE>
+// The attenuated forward of one image from its (f, mu) pairs (NEST: the walk's form).
+template <int DIM, int MODE, bool NEST>
 __global__ __launch_bounds__(kBlock) void k_forward_att_pairs(DevPlan P, const float* __restrict__ pairs,
                                                                float* __restrict__ sino)
 {
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_att_pairs(DevPlan P, const f
 #pragma unroll
     for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];   // from the detector side back
     AttFwdPairVisit v{image_rsrc(pairs, (int32_t)(P.n_units * 8)), R.scale, 0.0, 0.0};
-    walk<DIM>(P, R, v);
+    walk<DIM, NEST>(P, R, v);
     v.consume();
     sino[r] = (float)v.acc;
 }
@@ -683,7 +683,8 @@ template <int D, int M> struct FwdK { static auto fn() { return k_forward<D, M, 
 template <int D, int M> struct FwdNestK { static auto fn() { return k_forward<D, M, D == 3>; } };
 template <int D, int M> struct FwdAttK { static auto fn() { return k_forward_att<D, M>; } };
 template <int D, int M> struct FwdIlK { static auto fn() { return k_forward_il<D, M>; } };
-template <int D, int M> struct FwdAttPairK { static auto fn() { return k_forward_att_pairs<D, M>; } };
+template <int D, int M> struct FwdAttPairK { static auto fn() { return k_forward_att_pairs<D, M, false>; } };
+template <int D, int M> struct FwdAttPairNestK { static auto fn() { return k_forward_att_pairs<D, M, D == 3>; } };
 template <int D, int M> struct AdjAttK { static auto fn() { return k_adjoint_att<D, M>; } };
 template <int D, int M> struct ScatK { static auto fn() { return k_scatter<D, M>; } };
 template <int D, int M> struct CntK { static auto fn() { return k_counts<D, M>; } };
@@ -822,8 +823,10 @@ xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const f
                            mu + (int64_t)b * mu_stride, (float2*)p->d_att, P.n_units);
         xrt_status st = hip_fail(hipGetLastError(), "attenuation pairs launch");
         if (st != XRT_OK) return st;
-        st = dispatch<FwdAttPairK>(P, dim3(blocks_for(P.n_rays), 1u), s, (const float*)p->d_att,
-                                   sino + (int64_t)b * P.n_rays);
+        st = P.nest_z ? dispatch<FwdAttPairNestK>(P, dim3(blocks_for(P.n_rays), 1u), s, (const float*)p->d_att,
+                                                  sino + (int64_t)b * P.n_rays)
+                      : dispatch<FwdAttPairK>(P, dim3(blocks_for(P.n_rays), 1u), s, (const float*)p->d_att,
+                                              sino + (int64_t)b * P.n_rays);
         if (st != XRT_OK) return st;
     }
     return XRT_OK;
