@@ -139,8 +139,9 @@ def batched_bench(torch, dev, steps: int, tuning: dict):
     from paper_2006_00686_amd.batched import BatchGraph
     cfg = inputs.batched_workload()
     plans = [xrt.Plan(m["grid"], m["scan"], 0) for m in cfg["members"]]
-    for p in plans:
-        p.set_tuning(**tuning)
+    if tuning is not None:
+        for p in plans:
+            p.set_tuning(**tuning)
     bg = BatchGraph(xrt.Batch(plans))
     gen = torch.Generator(device=dev)
     for k, im in enumerate(bg.imgs):
@@ -182,7 +183,8 @@ def batched_bench(torch, dev, steps: int, tuning: dict):
     return {"workload": cfg["name"], "members": len(plans), "rays": rays, "volumes_zyx": [list(d) for d in dims],
             "ms_per_step": round(t_graph, 3), "mrays_per_s": round(rays / (t_graph * 1e-3) / 1e6, 1),
             "per_plan_launches_ms": round(t_eager, 3), "forward_persistent_ms": round(t_fwd_batch, 3),
-            "forward_per_plan_ms": round(t_fwd_each, 3), "launch": tuning,
+            "forward_per_plan_ms": round(t_fwd_each, 3),
+            "launch": tuning if tuning is not None else "each plan's own",
             "data": "synthetic: seeded uniform volumes"}
 
 
@@ -223,7 +225,7 @@ def main():
     M, V = plan.n_rays, plan.n_units
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
 
-    tuning = {"packet_cols": 0, "xcd_remap": 0}
+    tuning = plan.tuning()   # the library's choice for this plan
     if args.tune:
         from paper_2006_00686_amd import tune
         res = tune.autotune(plan, d_img, log=log)
@@ -305,7 +307,7 @@ def main():
     batched = None
     if not args.no_batched:
         log("[bench] batched launch: 16 uneven cone/helical problems")
-        batched = batched_bench(torch, dev, 3, tuning)
+        batched = batched_bench(torch, dev, 3, tuning if args.tune else None)
         log(f"[bench] batched {batched}")
 
     learned = None

@@ -15,7 +15,6 @@ import tempfile
 import numpy as np
 
 CANDIDATES = [(pc, xr) for pc in (0, 64, 32, 16) for xr in (0, 1)]
-DEFAULT = {"packet_cols": 0, "xcd_remap": 0}
 
 
 def cache_path() -> str:
@@ -77,9 +76,10 @@ def _device_name(plan) -> str:
 
 
 def apply_cached(plan, path: str | None = None) -> dict:
-    """Set the cached launch shape of the plan's geometry class, or the default."""
+    """Set the cached launch shape of the plan's geometry class, or the shape the library
+    chose when it created the plan."""
     sig = signature(plan.grid, plan.scan, _device_name(plan))
-    choice = valid_entry(load_cache(path).get(sig)) or dict(DEFAULT)
+    choice = valid_entry(load_cache(path).get(sig)) or dict(plan.default_tuning)
     plan.set_tuning(**choice)
     return choice
 

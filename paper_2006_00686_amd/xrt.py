@@ -185,6 +185,8 @@ class Plan:
         nr, nu = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.xrt_plan_sizes(h, ctypes.byref(nr), ctypes.byref(nu)), "xrt_plan_sizes")
         self.n_rays, self.n_units = nr.value, nu.value
+        # the launch shape the library chose at creation
+        self.default_tuning = self.tuning()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

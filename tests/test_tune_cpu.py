@@ -29,7 +29,8 @@ def test_invalid_entries_fall_back():
     assert tune.valid_entry({"packet_cols": 32, "xcd_remap": 2}) is None
     assert tune.valid_entry({"packet_cols": "32", "xcd_remap": 0}) is None
     assert tune.valid_entry({"packet_cols": 32, "xcd_remap": 1, "ms": 1.0}) == {"packet_cols": 32, "xcd_remap": 1}
-    assert tune.DEFAULT == {"packet_cols": 0, "xcd_remap": 0}
+    assert all(tune.valid_entry({"packet_cols": pc, "xcd_remap": xr}) == {"packet_cols": pc, "xcd_remap": xr}
+               for pc, xr in tune.CANDIDATES)
 
 
 def test_signature_separates_geometry_classes():
