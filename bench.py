@@ -197,7 +197,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched launch")
-    ap.add_argument("--tune", action="store_true", help="autotune the forward launch shape first (else the default)")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the forward launch-shape autotuner (untimed; default on) and keep the plan's own shape")
     ap.add_argument("--cpu-views-every", type=int, default=15)
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -307,7 +308,7 @@ def main():
     batched = None
     if not args.no_batched:
         log("[bench] batched launch: 16 uneven cone/helical problems")
-        batched = batched_bench(torch, dev, 3, tuning if args.tune else None)
+        batched = batched_bench(torch, dev, 3, None)
         log(f"[bench] batched {batched}")
 
     learned = None

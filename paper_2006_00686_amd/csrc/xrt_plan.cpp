@@ -474,11 +474,6 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
     // across (the 256^3 cone 2 %, 128-class grids 4-8 %); on 512-wide grids the lanes'
     // z crossings spread over more slabs and the flat form is 11-15 % faster
     D.nest_z = D.dim == 3 && std::max(D.nx, D.ny) <= 256 ? 1 : 0;
-    // with the nested walk, lanes that wait at z crossings fall behind their neighbours
-    // and a wave's loads spread over more cache lines; the XCD-aware block order keeps
-    // neighbouring waves on one L2 (256^3 cone 19.6 -> 19.0 ms; a plan's tuning can
-    // still change it)
-    if (D.nest_z) D.xcd_remap = 1;
     D.views = (const ViewGeom*)p->d_views;
     D.col_cs = (const double*)p->d_col;
     D.row_cs = (const double*)p->d_row;
