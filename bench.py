@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched launch")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip the forward launch-shape autotuner (untimed; default on) and keep the plan's own shape")
+    ap.add_argument("--launch", default=None, metavar="PC,XR",
+                    help="forward launch shape packet_cols,xcd_remap to use instead of the autotuner's")
     ap.add_argument("--cpu-views-every", type=int, default=15)
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
@@ -227,7 +229,12 @@ def main():
     log(f"[bench] rays {M}, units {V}, nnz {nnz} ({nnz / M:.1f} per ray)")
 
     tuning = plan.tuning()   # the library's choice for this plan
-    if args.tune:
+    if args.launch:
+        pc, xr = (int(v) for v in args.launch.split(","))
+        plan.set_tuning(pc, xr)
+        tuning = plan.tuning()
+        log(f"[bench] forward launch shape {tuning} (given)")
+    elif args.tune:
         from paper_2006_00686_amd import tune
         res = tune.autotune(plan, d_img, log=log)
         tuning = {"packet_cols": res["packet_cols"], "xcd_remap": res["xcd_remap"]}
