@@ -62,6 +62,20 @@ def test_attenuated_parity(X, name):
     H.assert_within_bar(adj, aref, ascl, what=f"attenuated adjoint {name}")
 
 
+def test_attenuated_forward_wide_grid(X):
+    """A grid wider than 256 units: the attenuated forward takes the walk's flat form."""
+    from tests.test_gpu_parity import WIDE_SCANS
+    for name, grid, scan in WIDE_SCANS:
+        plan = X.Plan(grid, scan)
+        rng = np.random.default_rng(23)
+        shape = tuple(plan.image_shape)
+        img = rng.uniform(0, 1, size=shape).astype(np.float32)
+        mu = rng.uniform(0, 0.05, size=shape).astype(np.float32)
+        got = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu).to(DEV)).cpu().numpy()
+        ref, scl = _bar(grid, scan, img, mu)
+        H.assert_within_bar(got, ref, scl, what=f"attenuated {name}")
+
+
 def test_zero_attenuation_is_the_transform(X):
     grid, scan = _scan("cone_flat")
     plan = X.Plan(grid, scan)
