@@ -124,7 +124,8 @@ constexpr int kWaves = kBlock / 64;
 // ZR: the detector has a row with v = 0, whose rays lie in the plane z = Sz.
 // CULL (helical scans, where the detector sees a band of z at a time): a wave skips a
 // block of 64 voxels when none of them has a candidate row on the detector; skipped
-// rows are exactly the ones that would add nothing.
+// rows are exactly the ones that would add nothing.  Without CULL (circular scans) every
+// source sits at the height sz0, and voxel heights are taken relative to it once.
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
 // vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling); vb_lo,
@@ -134,7 +135,7 @@ template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(
     DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
     int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz,
-    double vb_lo, double vb_hi)
+    double vb_lo, double vb_hi, double sz0)
 {
     // 1/v of every row followed by NR entries 0 for rows past the detector (their z
     // interval (0, 0) lies before tin > 0, so they are never hit), then the per-wave
@@ -167,11 +168,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int32_t kfirst = zc * 64 * KB, kbase = kfirst + lane;
     const __amdgpu_buffer_rsrc_t gsrc = make_rsrc(gT, (P.n_rays + kGatherPad) * 4);
 
+    // top face of the lane's voxel q; for a circular scan (every source at height sz0)
+    // already taken relative to the source, z - Sz
     double acc[KB], zb0[KB];
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
         acc[q] = 0.0;
-        zb0[q] = P.pz0 - (double)(kbase + 64 * q) * P.pdz;   // top face of the lane's voxel q
+        zb0[q] = P.pz0 - (double)(kbase + 64 * q) * P.pdz;
+        if constexpr (!CULL) zb0[q] = zb0[q] - sz0;
     }
 
     const int32_t slot = lane & ((1 << lg_slots) - 1), vlane = lane >> lg_slots;
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 auto head = [&](int q) {
                     // first candidate row: the smallest v = rel / tau of the voxel over
                     // tau in (tin, tout), in bin units
-                    const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
+                    const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
                     const double vlo = fmin(fma(rel0, sin_, vb_lo), fma(rel0, sout, vb_lo));
                     // rows outside the voxel's range fail C_low < C_up below on their own
                     // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 // often enough that evaluating it always is slower)
                 auto tail = [&](int q) {
                     if (NR > 2 && more[q]) {
-                        const double rel1 = zb0[q] - Sz, rel0 = rel1 - P.pdz;
+                        const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
 #pragma unroll
                         for (int ei = 2; ei < NR; ++ei) {
                             const int32_t r = r0[q] + ei;
@@ -529,14 +533,15 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
     const double vlast = P.vbase + (P.n_rows - 1) * P.dv;
     const double vmin = std::fmin(P.vbase, vlast), vmax = std::fmax(P.vbase, vlast);
     const double vb = -P.vbase * (1.0 / P.dv);
+    const double sz0 = p->sz0;
     if (p->zero_row >= 0)
-        hipLaunchKernelGGL((k_cone_gather<KB, NR, true, false>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
+        hipLaunchKernelGGL((k_cone_gather<KB, NR, true, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack, sz0);
     else
         hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack, sz0);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 

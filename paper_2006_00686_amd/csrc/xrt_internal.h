@@ -79,6 +79,7 @@ struct xrt_plan {
     int32_t gather_nr;  // bound on the detector rows one voxel's shadow covers per column
     int32_t gather_lgs; // log2 of the gather's column slots per view (0..6)
     int32_t helical;    // the source moves along z between views
+    double sz0;         // source height of the first view (of every view when !helical)
     // y-fastest copy of one image for the forward projection of views whose detector
     // u axis runs along y (3D scans, owned by the plan), or NULL
     float* d_imgT;

@@ -312,6 +312,7 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
     p->gather_lgs = 2;
     p->helical = 0;
     for (const ViewGeom& V : views) p->helical |= V.A[2] != views[0].A[2] ? 1 : 0;
+    p->sz0 = views.empty() ? 0.0 : views[0].A[2];
     // The detector columns that see a pixel are the interval between its corners' u
     // coordinates only when the pixel is in front of the source; require it of the
     // whole image box for every view, otherwise the plan uses the scatter adjoint.
