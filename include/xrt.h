@@ -263,7 +263,8 @@ xrt_status xrt_ray_transmission(xrt_plan* plan, const float* d_mu, float* d_w, i
  * 64, 32 or 16: a wavefront takes a packet of packet_cols detector columns x
  * (64 / packet_cols) rows of one view (ignored for ray lists).  xcd_remap = 1 gives
  * each of the 8 XCDs a contiguous range of packets (shared L2 working set).  A new plan
- * starts with the library's choice for its geometry (xrt_plan_get_tuning reports it). */
+ * starts linear (0, 0); the best shape depends on the geometry and is found by timing
+ * (the package's autotuner). */
 typedef struct {
     int32_t packet_cols;
     int32_t xcd_remap;

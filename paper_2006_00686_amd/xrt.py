@@ -185,7 +185,7 @@ class Plan:
         nr, nu = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.xrt_plan_sizes(h, ctypes.byref(nr), ctypes.byref(nu)), "xrt_plan_sizes")
         self.n_rays, self.n_units = nr.value, nu.value
-        # the launch shape the library chose at creation
+        # the launch shape the plan was created with
         self.default_tuning = self.tuning()
 
     def close(self):
