@@ -131,6 +131,36 @@ def learned_solve(torch, dev, tol: float = 1e-3):
             "weights": os.path.relpath(learned.default_weights(), ROOT), "stored_matrix": stored}
 
 
+def workloads_2d(torch, dev, steps: int = 20):
+    """The 2D workloads: forward + adjoint (AUTO) of one image per step, and the 2D
+    parallel case also as 64 images per launch each way; median of `steps` steps."""
+    from paper_2006_00686_amd import inputs, xrt
+    out = {}
+    for name, batch in (("par2d_128", 1), ("par2d_128", 64), ("fan2d_512", 1)):
+        cfg = inputs.workload(name)
+        plan = xrt.Plan(cfg["grid"], cfg["scan"], 0)
+        one = torch.from_numpy(inputs.make_image(cfg)).to(dev)
+        img = one.expand((batch,) + tuple(one.shape)).contiguous() if batch > 1 else one
+        sino = plan.forward(img)
+        back = plan.adjoint(sino)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.forward(img, out=sino)
+            plan.adjoint(sino, out=back)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        key = cfg["name"] + (f"_batch{batch}" if batch > 1 else "")
+        out[key] = {"ms_per_step": round(ms, 4), "images": batch,
+                    "mrays_per_s": round(plan.n_rays * batch / (ms * 1e-3) / 1e6, 1)}
+        plan.close()
+    return out
+
+
 def batched_bench(torch, dev, steps: int, tuning: dict):
     """16 uneven cone / helical problems: forward of all members in one persistent launch
     plus every member's adjoint, captured once in a graph and replayed; the same work as
@@ -197,6 +227,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner solve comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-problem batched launch")
+    ap.add_argument("--no-2d", dest="w2d", action="store_false", help="skip the 2D workloads")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip the forward launch-shape autotuner (untimed; default on) and keep the plan's own shape")
     ap.add_argument("--launch", default=None, metavar="PC,XR",
@@ -312,6 +343,11 @@ def main():
                   "mu": "uniform [0, 0.01) per unit length"}
     log(f"[bench] attenuated {attenuated}")
 
+    w2d = None
+    if args.w2d:
+        w2d = workloads_2d(torch, dev)
+        log(f"[bench] 2D workloads {w2d}")
+
     batched = None
     if not args.no_batched:
         log("[bench] batched launch: 16 uneven cone/helical problems")
@@ -353,6 +389,7 @@ def main():
         "learned": learned,
         "batched": batched,
         "attenuated": attenuated,
+        "workloads_2d": w2d,
     }
     print(json.dumps(out), flush=True)
 

@@ -2,7 +2,8 @@
 the 256^3 circular cone, from two rocprofv3 counter runs of the benchmark.
 
     cd /tmp && export TMPDIR=/tmp
-    B="python3 <repo>/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-learned --no-batched --copy-reference"
+    B="python3 <repo>/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-learned --no-batched --no-2d \
+       --no-tune --launch PC,XR --copy-reference"   # PC,XR: the shape bench.py's autotuner picks
     rocprofv3 --pmc FETCH_SIZE -d <out>/fetch -o run -- $B
     rocprofv3 --pmc WRITE_SIZE -d <out>/write -o run -- $B
     python -m paper_2006_00686_amd.traffic <out>/fetch/run_results.db <out>/write/run_results.db
@@ -24,7 +25,9 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20          # bench.py --copy-reference
-KERNELS = {"k_forward": r"::k_forward<", "k_cone_gather": r"::k_cone_gather<"}
+# the 3D forward (the workload's) and the cone gather; 2D forwards, if a run has any, and
+# the attenuated and batched forwards are other kernels
+KERNELS = {"k_forward": r"::k_forward<3, ", "k_cone_gather": r"::k_cone_gather<"}
 COPY = r"copyBuffer"
 
 

@@ -21,10 +21,11 @@ def test_scaled_bytes_per_launch(tmp_path):
     fetch, write = str(tmp_path / "fetch.db"), str(tmp_path / "write.db")
     fwd = "void xrt::(anonymous namespace)::k_forward<3, 1>(xrt::DevPlan, float const*)"
     att = "void xrt::(anonymous namespace)::k_forward_att<3, 1>(xrt::DevPlan, float const*)"
+    fwd2 = "void xrt::(anonymous namespace)::k_forward<2, 1, false>(xrt::DevPlan, float const*)"
     gat = "void xrt::(anonymous namespace)::k_cone_gather<4, 3, false, false>(xrt::DevPlan)"
     # the reference copy reads half of its 256 MiB in FETCH_SIZE units and writes all of
     # it; the runtime's small copies must not be taken for it
-    _db(fetch, "FETCH_SIZE", [(fwd, 1000.0), (fwd, 3000.0), (att, 9e9), (gat, 500.0),
+    _db(fetch, "FETCH_SIZE", [(fwd, 1000.0), (fwd, 3000.0), (att, 9e9), (fwd2, 7e9), (gat, 500.0),
                               ("__amd_rocclr_copyBuffer", 4.0), ("__amd_rocclr_copyBuffer", 131072.0)])
     _db(write, "WRITE_SIZE", [(fwd, 10.0), (gat, 20.0), ("__amd_rocclr_copyBuffer", 262144.0)])
     t = traffic.build(fetch, write)
