@@ -380,8 +380,10 @@ __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __r
             if constexpr (MODE == MODE_PARALLEL) {
                 u = fma(px, Bx, py * By);                        // p = u B (+ t E)
             } else if constexpr (MODE == MODE_DIVERGENT) {
+                // candidate range only (hits and lengths come from the exact clip below;
+                // the range's slack covers the hardware reciprocal's rounding)
                 const double e2 = Ex * Ex + Ey * Ey;             // |E|^2 = sdd^2
-                u = e2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+                u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
             } else {
                 u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));   // equiangular gamma
             }
@@ -462,8 +464,8 @@ __global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* 
             if constexpr (MODE == MODE_PARALLEL) {
                 u = fma(px, Bx, py * By);
             } else if constexpr (MODE == MODE_DIVERGENT) {
-                const double e2 = Ex * Ex + Ey * Ey;
-                u = e2 * fma(px, Bx, py * By) / fma(px, Ex, py * Ey);
+                const double e2 = Ex * Ex + Ey * Ey;   // as k_gather2d
+                u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
             } else {
                 u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));
             }
