@@ -122,6 +122,25 @@ xrt_status xrt_plan_destroy(xrt_plan* plan);
  * per batch member). */
 xrt_status xrt_plan_sizes(const xrt_plan* plan, int64_t* n_rays, int64_t* n_units);
 
+/* Which adjoint algorithm XRT_ADJ_AUTO runs on this plan, and for the voxel-driven cone
+ * gather (flat detector, circular or helical) the kernel variant the plan selects: the
+ * voxels along z each lane sums (1 for nz <= 64, 2 for nz <= 128, else 4 with further
+ * z chunks), the bound on the detector rows a voxel's shadow covers in one column (the
+ * candidate rows per voxel and record: 2, 3, 4, 6 or 8), the column slots per view of a
+ * record pass, whether the source moves along z (helical: the kernel skips blocks of
+ * voxels no ray of a record reaches), and the detector row with v = 0 (-1 if none).
+ * Fields that do not apply are 0 (zero_row -1).  No GPU work. */
+typedef struct {
+    int32_t algorithm;        /* XRT_ADJ_SCATTER or XRT_ADJ_GATHER */
+    int32_t voxels_per_lane;
+    int32_t row_bound;
+    int32_t column_slots;
+    int32_t helical;
+    int32_t zero_row;
+} xrt_adjoint_info;
+
+xrt_status xrt_plan_adjoint_info(const xrt_plan* plan, xrt_adjoint_info* out);
+
 /* Forward transform: d_sino[b][r] = sum_I d_img[b][I] * len(r, I) for b < batch.
  * Overwrites d_sino.  d_img and d_sino must not overlap. */
 xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch,
@@ -140,8 +159,9 @@ xrt_status xrt_ray_hit_counts(xrt_plan* plan, int64_t first, int64_t n, double e
 /* Hit lists of rays [first, first+n) (Algorithms 1 and 2: the 1D indices and
  * intersection lengths of each ray).  d_offsets is an int64 CSR row pointer [n+1]
  * (normally the exclusive prefix sum of xrt_ray_hit_counts with the same eps); row r
- * occupies d_idx/d_len[d_offsets[r] .. d_offsets[r+1]) and is filled in order of
- * increasing position along the ray.  No row writes past d_offsets[r+1]. */
+ * occupies d_idx/d_len[d_offsets[r] .. d_offsets[r+1]) and is sorted by increasing 1D
+ * index, the order of the paper's lists (Tables 1-5).  No row writes past
+ * d_offsets[r+1]; a row with more room than hits leaves the tail unwritten. */
 xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps,
                         const int64_t* d_offsets, int32_t* d_idx, float* d_len, void* stream);
 

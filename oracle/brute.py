@@ -84,3 +84,34 @@ def matrix(g: dict, lines_p, lines_th):
     """Dense projection matrix A[ray, unit] (tiny grids only)."""
     rows = [unit_lengths(g, lines_p[r], lines_th[r]).ravel() for r in range(len(lines_p))]
     return np.stack(rows, axis=0)
+
+
+def one_unit_lengths(g: dict, P, TH, unit):
+    """len(ray, unit) of many lines (P, TH: [n][d] points and directions) through one
+    unit, (k, j, i) in 3D or (j, i) in 2D: the same slab clip as unit_intervals, for one
+    box and many rays (sampled checks of the adjoint at full size)."""
+    P = np.asarray(P, dtype=np.float64)
+    TH = np.asarray(TH, dtype=np.float64)
+    nz = int(g.get("nz", 0))
+    dims = [("nx", "dx", "cx", +1), ("ny", "dy", "cy", -1)]
+    if nz > 0:
+        dims.append(("nz", "dz", "cz", -1))
+    q_of_axis = list(unit)[::-1]           # unit is (k, j, i) / (j, i); axes are x, y, z
+    n = P.shape[0]
+    L = np.full(n, -np.inf)
+    U = np.full(n, np.inf)
+    member = np.ones(n, dtype=bool)
+    for a, (kn, kd, kc, sgn) in enumerate(dims):
+        q = int(q_of_axis[a])
+        lo, hi = _axis_bounds(int(g[kn]), float(g.get(kd, 1.0)), float(g.get(kc, 0.0)), sgn)
+        lo, hi = lo[q], hi[q]
+        d = TH[:, a]
+        mv = d != 0.0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t0 = (lo - P[:, a]) / d
+            t1 = (hi - P[:, a]) / d
+        L = np.where(mv, np.maximum(L, np.minimum(t0, t1)), L)
+        U = np.where(mv, np.minimum(U, np.maximum(t0, t1)), U)
+        inside = (lo <= P[:, a]) & (P[:, a] < hi) if sgn > 0 else (lo < P[:, a]) & (P[:, a] <= hi)
+        member &= mv | inside
+    return np.where(member, np.maximum(U - L, 0.0), 0.0)

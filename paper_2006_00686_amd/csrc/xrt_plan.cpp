@@ -615,6 +615,25 @@ xrt_status adjoint_impl(xrt_plan* plan, const float* d_sino, float* d_img, int32
 
 }  // namespace
 
+xrt_status xrt_plan_adjoint_info(const xrt_plan* plan, xrt_adjoint_info* out)
+{
+    if (!plan || !out) { set_error("null argument"); return XRT_E_ARG; }
+    *out = xrt_adjoint_info{XRT_ADJ_SCATTER, 0, 0, 0, 0, -1};
+    if (plan->kind == XRT_CONE_FLAT && plan->gather_ok) {
+        const int32_t nz = plan->dp.nz, nr = plan->gather_nr;
+        out->algorithm = XRT_ADJ_GATHER;
+        out->voxels_per_lane = nz <= 64 ? 1 : nz <= 128 ? 2 : 4;
+        // the kernel instantiations of launch_adjoint_cone_gather
+        out->row_bound = nr <= 2 ? 2 : nr <= 4 ? nr : nr <= 6 ? 6 : 8;
+        out->column_slots = 1 << plan->gather_lgs;
+        out->helical = plan->helical;
+        out->zero_row = plan->zero_row;
+    } else if (plan->gather2d_ok) {
+        out->algorithm = XRT_ADJ_GATHER;
+    }
+    return XRT_OK;
+}
+
 xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, int32_t mode,
                        void* stream)
 {

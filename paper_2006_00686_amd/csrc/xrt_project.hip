@@ -634,6 +634,55 @@ __global__ __launch_bounds__(kBlock) void k_counts(DevPlan P, int32_t first, int
     counts[t] = v.n;
 }
 
+// Entries [lo, hi) of a row in reverse order.
+__device__ void reverse_entries(int32_t* __restrict__ idx, float* __restrict__ len, int32_t lo, int32_t hi)
+{
+    for (--hi; lo < hi; ++lo, --hi) {
+        const int32_t a = idx[lo];
+        idx[lo] = idx[hi];
+        idx[hi] = a;
+        const float b = len[lo];
+        len[lo] = len[hi];
+        len[hi] = b;
+    }
+}
+
+// Sort a row written in order along the ray by 1D index I = (k ny + j) nx + i.  Along a
+// line each of k, j and i is monotone, so the row is ordered lexicographically by
+// (+-k, +-j, +-i) with the signs of the ray's direction: reversing the whole row where k
+// falls, then every run of one k where j falls, then every run of one (k, j) where i
+// falls sorts it.  A final insertion pass (no work on a sorted row) makes the order
+// exact whatever the row's order was.
+__device__ void sort_row(int32_t* __restrict__ idx, float* __restrict__ len, int32_t n, int32_t nx, int32_t nxy)
+{
+    const int32_t key[3] = {nxy, nx, 1};
+    for (int lev = 0; lev < 3; ++lev) {
+        const int32_t d = key[lev];
+        for (int32_t a = 0; a < n;) {
+            int32_t b = a + 1;
+            if (lev > 0) {
+                const int32_t run = idx[a] / key[lev - 1];
+                while (b < n && idx[b] / key[lev - 1] == run) ++b;
+            } else {
+                b = n;
+            }
+            if (idx[a] / d > idx[b - 1] / d) reverse_entries(idx, len, a, b);
+            a = b;
+        }
+    }
+    for (int32_t m = 1; m < n; ++m) {
+        const int32_t I = idx[m];
+        const float l = len[m];
+        int32_t q = m - 1;
+        for (; q >= 0 && idx[q] > I; --q) {
+            idx[q + 1] = idx[q];
+            len[q + 1] = len[q];
+        }
+        idx[q + 1] = I;
+        len[q + 1] = l;
+    }
+}
+
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_hits(DevPlan P, int32_t first, int32_t n, double eps,
                                                   const int64_t* __restrict__ off,
@@ -647,6 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(DevPlan P, int32_t first, int32
     const int32_t cap = (int32_t)(off[t + 1] - o);
     EmitVisit v{idx + o, len + o, eps / R.scale, R.scale, 0, cap};
     walk<DIM>(P, R, v);
+    // the order of the paper's hit lists (Algorithms 1 and 2; the tables of Sec. 5)
+    sort_row(idx + o, len + o, v.n, P.nx, P.nx * P.ny);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_zero(float* __restrict__ dst, int64_t n)

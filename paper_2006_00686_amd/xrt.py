@@ -43,6 +43,11 @@ class Scan(ctypes.Structure):
                 ("ray_params", _dp), ("n_rays", ctypes.c_int64)]
 
 
+class AdjointInfo(ctypes.Structure):
+    _fields_ = [("algorithm", ctypes.c_int32), ("voxels_per_lane", ctypes.c_int32), ("row_bound", ctypes.c_int32),
+                ("column_slots", ctypes.c_int32), ("helical", ctypes.c_int32), ("zero_row", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("packet_cols", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
 
@@ -76,6 +81,7 @@ def _lib():
         lib.xrt_conv3x3_wgrad_workspace.restype = i64
         lib.xrt_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, i64, vp, vp]
         lib.xrt_precond_apply.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        lib.xrt_plan_adjoint_info.argtypes = [vp, ctypes.POINTER(AdjointInfo)]
         lib.xrt_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         lib.xrt_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         lib.xrt_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
@@ -353,6 +359,14 @@ class Plan:
                "xrt_ray_transmission")
         return out
 
+    def adjoint_info(self) -> dict:
+        """The adjoint AUTO runs and the cone gather's kernel variant (xrt_plan_adjoint_info)."""
+        info = AdjointInfo()
+        _check(_lib().xrt_plan_adjoint_info(self._h, ctypes.byref(info)), "xrt_plan_adjoint_info")
+        out = {f: getattr(info, f) for f, _ in AdjointInfo._fields_}
+        out["algorithm"] = {1: "scatter", 2: "gather"}[out["algorithm"]]
+        return out
+
     def hit_counts(self, first: int = 0, n: int | None = None, eps: float = 0.0) -> torch.Tensor:
         n = self.n_rays - first if n is None else n
         out = torch.empty(n, dtype=torch.int32, device=f"cuda:{self.device}")
@@ -361,7 +375,7 @@ class Plan:
         return out
 
     def hits(self, first: int = 0, n: int | None = None, eps: float = 0.0):
-        """(offsets[n+1], idx, len) CSR of rays [first, first+n), rows in traversal order."""
+        """(offsets[n+1], idx, len) CSR of rays [first, first+n), rows sorted by 1D index."""
         counts = self.hit_counts(first, n, eps)
         n = counts.numel()
         offs = offsets_from_counts(counts)

@@ -1,0 +1,198 @@
+"""GPU: the voxel-driven cone adjoint voxel by voxel against the FP64 oracle on every
+kernel variant the workloads run (Introduction: the adjoint is the transpose of the
+projection matrix; eq. range_length_3D gives each length).
+
+* Deep, narrow volumes (the oracle adjoint of every ray stays cheap) that take 2 voxels
+  per lane (65 <= nz <= 128) and 4 voxels per lane (nz > 128, one and two z chunks),
+  circular with and without a detector row at v = 0, with 3 to 8 candidate rows per
+  voxel, and helical with 2 and 4 voxels per lane (the 4-voxel helical kernel skips the
+  blocks of voxels no ray of a record reaches).
+* The 256^3 cone of the benchmark and a 512 x 512 x 256 helical member of the batched
+  workload at full size: sampled voxels, each summed over every view from the rays of
+  a window around its shadow, clipped against the voxel by the oracle's brute force.
+* The 2D fan workload's adjoint in full.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import tests.helpers as H
+from oracle import brute as obrute
+from oracle import geometry as ogeom
+from paper_2006_00686_amd import inputs
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+@pytest.fixture(scope="module")
+def xrt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_00686_amd import xrt as X
+    X.library()
+    return X
+
+
+def _helix(nv, turns, z0, z1, **kw):
+    return dict(kind="cone_flat", angles=np.arange(nv) * 2 * PI * turns / nv, view_z=np.linspace(z0, z1, nv), **kw)
+
+
+# name, grid, scan, expected voxels per lane, expected helical flag
+DEEP = [
+    ("kb2_zero_row", dict(nx=12, ny=10, nz=100, dx=1.0, dy=1.0, dz=1.0, cx=0.3, cy=-0.2, cz=0.1),
+     dict(kind="cone_flat", angles=np.linspace(0.05, 2 * PI, 24, endpoint=False), ncols=25, nrows=171, du=1.0,
+          dv=1.0, u0=0.1, v0=0.0, sod=100.0, sdd=150.0), 2, 0),
+    ("kb2_fine_rows", dict(nx=12, ny=10, nz=90, dx=1.0, dy=1.1, dz=0.9, cx=0.0, cy=0.0, cz=0.4),
+     dict(kind="cone_flat", angles=np.linspace(0.1, 2 * PI, 20, endpoint=False), ncols=26, nrows=320, du=1.0,
+          dv=0.5, u0=0.0, v0=0.13, sod=100.0, sdd=150.0), 2, 0),
+    ("kb4_one_chunk", dict(nx=12, ny=10, nz=160, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0),
+     dict(kind="cone_flat", angles=np.linspace(0.0, 2 * PI, 24, endpoint=False), ncols=25, nrows=280, du=1.0,
+          dv=1.0, u0=0.0, v0=0.0, sod=100.0, sdd=150.0), 4, 0),
+    ("kb4_two_chunks_zero_row", dict(nx=10, ny=12, nz=300, dx=1.0, dy=1.0, dz=1.0, cx=-0.4, cy=0.3, cz=0.0),
+     dict(kind="cone_flat", angles=np.linspace(0.2, 2 * PI, 16, endpoint=False), ncols=27, nrows=501, du=1.0,
+          dv=1.0, u0=0.0, v0=0.0, sod=300.0, sdd=450.0), 4, 0),
+    ("kb4_helical", dict(nx=12, ny=10, nz=200, dx=1.0, dy=1.0, dz=1.0, cx=0.2, cy=0.1, cz=0.0),
+     _helix(30, 3, -110.0, 110.0, ncols=27, nrows=64, du=1.0, dv=1.0, u0=0.0, v0=0.0, sod=300.0, sdd=450.0), 4, 1),
+    ("kb4_helical_fine_rows", dict(nx=10, ny=10, nz=150, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0),
+     _helix(24, 2, -80.0, 80.0, ncols=25, nrows=96, du=1.0, dv=0.5, u0=0.05, v0=0.0, sod=300.0, sdd=450.0), 4, 1),
+    ("kb2_helical", dict(nx=12, ny=10, nz=100, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.2),
+     _helix(20, 2, -60.0, 60.0, ncols=27, nrows=48, du=1.0, dv=1.0, u0=0.0, v0=0.0, sod=300.0, sdd=450.0), 2, 1),
+]
+
+
+@pytest.mark.parametrize("name,grid,scan,kb,helical", DEEP, ids=[d[0] for d in DEEP])
+def test_deep_gather_parity(xrt, name, grid, scan, kb, helical):
+    plan = xrt.Plan(grid, scan)
+    info = plan.adjoint_info()
+    assert info["algorithm"] == "gather" and info["voxels_per_lane"] == kb and info["helical"] == helical, info
+    print(f"[deep gather] {name}: {info}", flush=True)
+    rng = np.random.default_rng(17)
+    sino = rng.normal(size=inputs.sino_shape(scan)).astype(np.float32)
+    d = torch.from_numpy(sino).to("cuda:0")
+    got = plan.adjoint(d, mode="gather").cpu().numpy()
+    ref, scl = H.adjoint_bar(grid, scan, sino)
+    H.assert_within_bar(got, ref, scl, what=f"gather adjoint {name}")
+    sc = plan.adjoint(d, mode="scatter").cpu().numpy()
+    H.assert_within_bar(sc, ref, scl, what=f"scatter adjoint {name}")
+
+
+def test_deep_gather_variants_are_covered(xrt):
+    """The cases above reach the row bounds and the v = 0 row they are meant to."""
+    seen = set()
+    for name, grid, scan, kb, helical in DEEP:
+        info = xrt.Plan(grid, scan).adjoint_info()
+        seen.add((info["voxels_per_lane"], info["helical"], info["row_bound"]))
+        if name.endswith("zero_row"):
+            assert info["zero_row"] >= 0, (name, info)
+    assert {(2, 0), (4, 0), (2, 1), (4, 1)} <= {(a, b) for a, b, _ in seen}
+    assert max(r for _, _, r in seen) >= 6 and min(r for _, _, r in seen) <= 4
+
+
+# ------------------------------------------------------------------ full size, sampled voxels
+
+def _cone_windows(grid, scan, v, unit, margin=2):
+    """Detector columns and rows around the shadow of one voxel in view v (plain pinhole
+    projection of its corners; the caller checks that the window's border misses it)."""
+    k, j, i = unit
+    nx, ny, nz = grid["nx"], grid["ny"], grid["nz"]
+    xs = grid.get("cx", 0.0) + (np.array([i, i + 1]) - nx / 2.0) * grid["dx"]
+    ys = grid.get("cy", 0.0) + (ny / 2.0 - np.array([j, j + 1])) * grid["dy"]
+    zs = grid.get("cz", 0.0) + (nz / 2.0 - np.array([k, k + 1])) * grid["dz"]
+    a = scan["angles"][v]
+    h = 0.0 if scan.get("view_z") is None else scan["view_z"][v]
+    S = np.array([-scan["sod"] * np.cos(a), -scan["sod"] * np.sin(a), h])
+    e = np.array([np.cos(a), np.sin(a), 0.0])
+    b = np.array([-np.sin(a), np.cos(a), 0.0])
+    X = np.array([[x, y, z] for x in xs for y in ys for z in zs]) - S
+    depth = X @ e
+    u = scan["sdd"] * (X @ b) / depth
+    w = scan["sdd"] * X[:, 2] / depth
+    cc = (u - scan.get("u0", 0.0)) / scan["du"] + (scan["ncols"] - 1) / 2.0
+    rr = (w - scan.get("v0", 0.0)) / scan["dv"] + (scan["nrows"] - 1) / 2.0
+    c0, c1 = int(np.floor(cc.min())) - margin, int(np.ceil(cc.max())) + margin
+    r0, r1 = int(np.floor(rr.min())) - margin, int(np.ceil(rr.max())) + margin
+    return (max(c0, 0), min(c1, scan["ncols"] - 1), c0 >= 0, c1 <= scan["ncols"] - 1,
+            max(r0, 0), min(r1, scan["nrows"] - 1), r0 >= 0, r1 <= scan["nrows"] - 1)
+
+
+def sampled_cone_adjoint(grid, scan, sino, units):
+    """Oracle adjoint (and its scale sum |g| len) at the given voxels: for every view, the
+    rays of a window around the voxel's shadow clipped against the voxel (brute force)."""
+    nv, nr, nc = sino.shape
+    ref = np.zeros(len(units))
+    scl = np.zeros(len(units))
+    for v in range(nv):
+        one = dict(scan)
+        one["angles"] = np.asarray(scan["angles"])[v:v + 1]
+        if scan.get("view_z") is not None:
+            one["view_z"] = np.asarray(scan["view_z"])[v:v + 1]
+        p, th = ogeom.expand(one)
+        for q, unit in enumerate(units):
+            c0, c1, cin0, cin1, r0, r1, rin0, rin1 = _cone_windows(grid, scan, v, unit)
+            if c0 > c1 or r0 > r1:
+                continue
+            rows, cols = np.meshgrid(np.arange(r0, r1 + 1), np.arange(c0, c1 + 1), indexing="ij")
+            rays = (rows * nc + cols).ravel()
+            ln = obrute.one_unit_lengths(grid, p[rays], th[rays], unit).reshape(rows.shape)
+            # the shadow lies inside the window: no hit on a border that is not the detector's
+            for inner, edge in ((cin0, ln[:, 0]), (cin1, ln[:, -1]), (rin0, ln[0, :]), (rin1, ln[-1, :])):
+                assert not inner or np.all(edge == 0.0), (v, unit)
+            gv = sino[v, r0:r1 + 1, c0:c1 + 1].astype(np.float64)
+            ref[q] += float((gv * ln).sum())
+            scl[q] += float((np.abs(gv) * ln).sum())
+    return ref, scl
+
+
+def _sample_units(grid, n, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = grid["nx"], grid["ny"], grid["nz"]
+    fixed = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, ny // 2, nx // 2), (nz - 1, 0, nx // 2),
+             (63, ny // 3, nx // 4), (64, ny // 3, nx // 4), (127, 1, nx - 2), (128, ny - 2, 1)]
+    units = [u for u in fixed if u[0] < nz]
+    while len(units) < n:
+        units.append((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
+    return units
+
+
+def _check_sampled(xrt, grid, scan, n_units, seed, what):
+    plan = xrt.Plan(grid, scan)
+    info = plan.adjoint_info()
+    print(f"[sampled gather] {what}: {info}", flush=True)
+    assert info["algorithm"] == "gather" and info["voxels_per_lane"] == 4
+    rng = np.random.default_rng(seed)
+    sino = rng.normal(size=plan.sino_shape).astype(np.float32)
+    got = plan.adjoint(torch.from_numpy(sino).to("cuda:0")).cpu().numpy()
+    units = _sample_units(grid, n_units, seed + 1)
+    ref, scl = sampled_cone_adjoint(grid, scan, sino, units)
+    assert np.count_nonzero(scl) >= n_units // 2
+    H.assert_within_bar(np.array([got[u] for u in units]), ref, scl, what=what,
+                        floor=H.ABS_FLOOR * float(scl.max()))
+    return info
+
+
+def test_cone_256_sampled_adjoint(xrt):
+    """The benchmark's own adjoint (4 voxels per lane, 3 candidate rows, no v = 0 row)."""
+    cfg = inputs.workload("cone_256")
+    info = _check_sampled(xrt, cfg["grid"], cfg["scan"], 48, 91, "cone_256 sampled adjoint")
+    assert info["helical"] == 0 and info["zero_row"] == -1
+
+
+def test_helical_512_sampled_adjoint(xrt):
+    """A 512 x 512 x 256 helical member of the batched workload (2160 views)."""
+    wl = inputs.batched_workload()
+    m = next(m for m in wl["members"] if m["scan"].get("view_z") is not None
+             and (m["grid"]["nx"], m["grid"]["nz"]) == (512, 256))
+    info = _check_sampled(xrt, m["grid"], m["scan"], 24, 92, "helical 512x512x256 sampled adjoint")
+    assert info["helical"] == 1
+
+
+def test_fan2d_512_full_adjoint(xrt):
+    cfg = inputs.workload("fan2d_512")
+    plan = xrt.Plan(cfg["grid"], cfg["scan"])
+    assert plan.adjoint_info()["algorithm"] == "gather"
+    sino = np.random.default_rng(93).normal(size=plan.sino_shape).astype(np.float32)
+    got = plan.adjoint(torch.from_numpy(sino).to("cuda:0")).cpu().numpy()
+    ref, scl = H.adjoint_bar(cfg["grid"], cfg["scan"], sino)
+    H.assert_within_bar(got, ref, scl, what="fan2d_512 adjoint")

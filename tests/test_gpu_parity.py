@@ -42,8 +42,8 @@ def gpu_hits(xrt, grid, scan, eps=0.0):
     rows = []
     for r in range(len(offs) - 1):
         a, b = offs[r], offs[r + 1]
-        o = np.argsort(idx[a:b], kind="stable")
-        rows.append((idx[a:b][o].astype(np.int64), ln[a:b][o].astype(np.float64)))
+        # rows come sorted by 1D index from the kernel (the paper's list order)
+        rows.append((idx[a:b].astype(np.int64), ln[a:b].astype(np.float64)))
     return rows
 
 
@@ -111,6 +111,15 @@ def test_hit_sets_generic_rays(xrt, d3):
         gi, gl = rows[k]
         np.testing.assert_array_equal(gi, oi, err_msg=f"ray {r}")
         np.testing.assert_allclose(gl, ol, rtol=2e-6, atol=1e-6, err_msg=f"ray {r}")
+    # hit counts (the CSR row lengths) against the oracle's, at eps = 0 and inside the
+    # range of the lengths (generic rays: no length within 1e-3 of either threshold)
+    plan = xrt.Plan(grid, scan)
+    for eps in (0.0, 0.25):
+        want = ocore.hit_counts_lines(grid, p[keep], th[keep], eps)
+        ok = np.array([np.all(np.abs(ocore.ray_hits_line(grid, p[r], th[r], 0.0)[1] - eps) >= 1e-3)
+                       for r in keep])
+        got = plan.hit_counts(eps=eps).cpu().numpy()
+        np.testing.assert_array_equal(got[ok], want[ok])
 
 
 # ------------------------------------------------------------------ forward / adjoint per scan kind

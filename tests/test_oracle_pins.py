@@ -261,6 +261,44 @@ def test_oracle_matches_brute_force(d3):
             np.testing.assert_allclose(dense, ref, atol=1e-10)
 
 
+@pytest.mark.parametrize("d3", [False, True])
+def test_hit_counts_match_brute_force(d3):
+    """Hit counts per ray (the row lengths of the projection matrix) equal the number of
+    units whose brute-force clip is longer than eps, on generic rays (every hit at least
+    1e-3 long, so the count does not depend on rounding) and for eps below and inside the
+    range of the lengths."""
+    rng = np.random.default_rng(31 + d3)
+    for trial in range(30):
+        g = _random_grid(rng, d3)
+        rays = (inputs.random_rays3d if d3 else inputs.random_rays2d)(40, 8.0, 300 + trial)
+        p, th = (G.par3d_lines(*rays.T) if d3 else G.par2d_lines(*rays.T))
+        dense = np.stack([brute.unit_lengths(g, p[r], th[r]).ravel() for r in range(len(p))])
+        generic = np.all((dense == 0.0) | (dense >= 1e-3), axis=1)
+        for eps in (0.0, 0.3):
+            got = core.hit_counts_lines(g, p, th, eps)
+            want = (dense > max(eps, 1e-9)).sum(axis=1)
+            np.testing.assert_array_equal(got[generic], want[generic])
+        # a count of zero exactly for the rays that miss the box
+        assert np.all((core.hit_counts_lines(g, p, th, 0.0) == 0) == (dense.max(axis=1) <= 1e-12))
+
+
+@pytest.mark.parametrize("d3", [False, True])
+def test_one_unit_lengths_match_brute_force(d3):
+    """The per-unit clip of many rays (used for sampled checks at full size) equals the
+    dense brute force unit by unit, axis-parallel rays on grid planes included."""
+    rng = np.random.default_rng(41 + d3)
+    for trial in range(12):
+        g = _random_grid(rng, d3)
+        rays = (inputs.random_rays3d if d3 else inputs.random_rays2d)(30, 8.0, 500 + trial)
+        rays[:4, -1] = 0.0                  # phi2 = 0 (3D) or phi = 0 (2D): axis-parallel
+        p, th = (G.par3d_lines(*rays.T) if d3 else G.par2d_lines(*rays.T))
+        shape = inputs.image_shape(g)
+        dense = np.stack([brute.unit_lengths(g, p[r], th[r]) for r in range(len(p))])
+        for unit in np.ndindex(*shape):
+            got = brute.one_unit_lengths(g, p, th, unit)
+            np.testing.assert_array_equal(got, dense[(slice(None),) + unit])
+
+
 def test_oracle_forward_adjoint_match_explicit_matrix():
     rng = np.random.default_rng(5)
     g = dict(nx=5, ny=4, nz=3, dx=0.9, dy=1.3, dz=0.7, cx=0.4, cy=-0.2, cz=0.3)
