@@ -211,20 +211,26 @@ def default_weights() -> str:
 
 def evaluate(plan: X.Plan, P: ConvPreconditioner, g: torch.Tensor, tol: float = 1e-3, max_iters: int = 3000,
              check_every: int = 1, op=None) -> dict:
-    """Wall time from data on the device to the first iterate whose recursive residual
-    satisfies ||r|| <= tol ||g|| for every problem of the batch: plain CGLS and CGLS
-    right-preconditioned by P, with the on-the-fly transform of the plan or the operator
-    `op` (e.g. the stored matrix).  Both solvers run once untimed first (kernel loading)."""
+    """Wall time from data on the device to the first image whose residual satisfies
+    ||A f - g|| <= tol ||g|| for every problem of the batch (the recursive residual
+    proposes the stop, the true residual with FP64 norms confirms it inside the timed
+    region): plain CGLS and CGLS right-preconditioned by P, with the on-the-fly transform
+    of the plan or the operator `op` (e.g. the stored matrix).  Both solvers run once
+    untimed first (kernel loading)."""
     from . import solvers
     op = op if op is not None else solvers.PlanOperator(plan)
     solvers.cgls(op, g, 2, tol, check_every)
     solvers.pcgls(op, P, g, 2, tol, check_every, fallback=False)
     xc, ic = solvers.cgls(op, g, max_iters, tol, check_every)
     xp, ip = solvers.pcgls(op, P, g, max_iters, tol, check_every)
+    def last(h):
+        return h[-1] if h else None
+
     return dict(cgls=dict(seconds=ic.seconds, iterations=ic.iterations, converged=ic.converged,
-                          rel_residual=ic.rel_residual[-1] if ic.rel_residual else None),
+                          rel_residual=last(ic.rel_residual), true_residual=last(ic.true_residual),
+                          confirmations=len(ic.true_residual)),
                 pcgls=dict(seconds=ip.seconds, iterations=ip.iterations, converged=ip.converged,
-                           rel_residual=ip.rel_residual[-1] if ip.rel_residual else None,
-                           fallback=ip.fallback, failure=ip.failure),
+                           rel_residual=last(ip.rel_residual), true_residual=last(ip.true_residual),
+                           confirmations=len(ip.true_residual), fallback=ip.fallback, failure=ip.failure),
                 speedup=ic.seconds / ip.seconds if ip.seconds > 0 else None,
                 images=(xc, xp))

@@ -113,27 +113,12 @@ class MatrixOperator:
         return self._product(self.At, y, out, self.range_shape, self.domain_shape)
 
 
-class RightPreconditioned:
-    """A P with a linear preconditioner P (apply / adjoint on the image space)."""
-
-    def __init__(self, op: PlanOperator, P):
-        self.op = op
-        self.P = P
-        self.domain_shape = op.domain_shape
-        self.range_shape = op.range_shape
-
-    def apply(self, z: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self.op.apply(self.P.apply(z), out=out)
-
-    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self.P.adjoint(self.op.adjoint(y), out=out)
-
-
 @dataclass
 class SolveInfo:
     iterations: int = 0
     converged: bool = False
     rel_residual: list = field(default_factory=list)   # recursive ||r|| / ||g||, per check
+    true_residual: list = field(default_factory=list)  # ||g - A f|| / ||g|| (FP64 norms), per confirmation
     seconds: float = 0.0
     failure: str | None = None     # "nonfinite" or "stall" when the iteration was abandoned
     fallback: bool = False         # result comes from plain CGLS after a failed PCGLS
@@ -149,15 +134,25 @@ class _Dots:
 
 
 def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
-         finish=None, stall_checks: int = 0, stall_ratio: float = 0.999,
-         graph: bool = False) -> tuple[torch.Tensor, SolveInfo]:
-    """CGLS (x0 = 0): minimises ||op(x) - g|| for every batch member.
+         stall_checks: int = 0, stall_ratio: float = 0.999, graph: bool = False, P=None,
+         confirm: bool = True) -> tuple[torch.Tensor, SolveInfo]:
+    """CGLS (x0 = 0): minimises ||op(x) - g|| for every batch member; with a linear
+    preconditioner P (apply / adjoint on the image space), right-preconditioned CGLS:
+    min ||op(P z) - g|| with the image f = P z.
 
-    Stops after `iters` iterations or once every member's recursive residual satisfies
-    ||r|| <= tol ||g||.  `finish(z)` maps the iterate to the image (the preconditioner for
-    right-preconditioned CGLS).  With a tolerance, the iteration is abandoned (info.failure)
-    when the worst residual is not finite, or, if stall_checks > 0, when it has not dropped
-    below stall_ratio times its value stall_checks checks earlier.
+    With P the image is accumulated directly, f += alpha (P p), from the same P p whose
+    projection q = op(P p) updates the residual r -= alpha q.  So r tracks g - op(f) of
+    the returned image up to FP32 rounding even where P is linear only up to rounding
+    (BF16 hidden activations); P applied to the accumulated z would not be.
+
+    Stops after `iters` iterations or once every member's residual satisfies
+    ||r|| <= tol ||g||.  With confirm=True (and a tolerance), the recursive residual only
+    proposes the stop: the true residual ||g - op(f)|| / ||g|| is then computed on the GPU
+    (FP32 residual vector, FP64 norms) and the iteration goes on until it satisfies the
+    tolerance for every member too (inside the timed region, info.true_residual).  With a
+    tolerance, the iteration is abandoned (info.failure) when the worst residual is not
+    finite, or, if stall_checks > 0, when it has not dropped below stall_ratio times its
+    value stall_checks checks earlier.
 
     graph=True captures `check_every` iterations in a HIP graph once (after a first
     iteration run directly, which loads every kernel) and replays it between checks: the
@@ -171,29 +166,45 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
     x = torch.zeros((batch,) + tuple(op.domain_shape), dtype=torch.float32, device=dev)
     r = g.clone()
     s = op.adjoint(r)
+    if P is not None:
+        s = P.adjoint(s)
     p = s.clone()
     q = torch.empty_like(r)
+    w = torch.empty_like(x) if P is not None else p      # image of the search direction, P p
+    t = torch.empty_like(x) if P is not None else s      # op^T r before P^T
     gamma, gamma_new, delta, rr, gg = (torch.empty(batch, **f64) for _ in range(5))
     dots(s, s, gamma)
     dots(g, g, gg)
     info = SolveInfo()
 
     def step():
-        op.apply(p, out=q)
+        if P is not None:
+            P.apply(p, out=w)
+        op.apply(w, out=q)
         dots(q, q, delta)
-        X.vec_axpy_ratio(gamma, delta, 1.0, p, x, batch)     # x += (gamma / delta) p
+        X.vec_axpy_ratio(gamma, delta, 1.0, w, x, batch)     # f += (gamma / delta) P p
         X.vec_axpy_ratio(gamma, delta, -1.0, q, r, batch)    # r -= (gamma / delta) q
-        op.adjoint(r, out=s)
+        op.adjoint(r, out=t)
+        if P is not None:
+            P.adjoint(t, out=s)
         dots(s, s, gamma_new)
         X.vec_xpby_ratio(gamma_new, gamma, s, p, batch)      # p = s + (gamma' / gamma) p
         torch.mul(gamma_new, 1.0, out=gamma)                  # gamma = gamma' (a kernel)
+
+    def true_worst() -> float:
+        op.apply(x, out=q)
+        X.vec_axpby(1.0, g, -1.0, q)                          # q = g - op(f)
+        dots(q, q, rr)
+        worst = float(torch.sqrt(rr / gg).max().item())
+        info.true_residual.append(worst)
+        return worst
 
     def check() -> bool:
         """Record the worst residual; True when the iteration ends here."""
         dots(r, r, rr)
         worst = float(torch.sqrt(rr / gg).max().item())
         info.rel_residual.append(worst)
-        if worst <= tol:
+        if worst <= tol and (not confirm or true_worst() <= tol):
             info.converged = True
             return True
         if not math.isfinite(worst):
@@ -223,24 +234,23 @@ def cgls(op, g: torch.Tensor, iters: int, tol: float | None = None, check_every:
         info.iterations = it
         if tol is not None and check():
             break
-    out = finish(x) if finish is not None else x
     torch.cuda.synchronize(dev)
     info.seconds = time.perf_counter() - t0
-    return out, info
+    return x, info
 
 
 def pcgls(op, P, g: torch.Tensor, iters: int, tol: float | None = None, check_every: int = 5,
-          fallback: bool = True, stall_checks: int = 4, graph: bool = False):
-    """Right-preconditioned CGLS: min ||A P z - g||, image f = P z.
+          fallback: bool = True, stall_checks: int = 4, graph: bool = False, confirm: bool = True):
+    """Right-preconditioned CGLS: min ||A P z - g||, image f = P z (accumulated directly).
 
     With a tolerance and fallback=True, a preconditioned run whose worst residual becomes
     non-finite or stalls is discarded and plain CGLS solves the problem from x0 = 0
     (info.fallback and info.failure are set; info.seconds covers both runs)."""
-    x, info = cgls(RightPreconditioned(op, P), g, iters, tol, check_every, finish=P.apply,
-                   stall_checks=stall_checks if tol is not None else 0, graph=graph)
+    x, info = cgls(op, g, iters, tol, check_every, stall_checks=stall_checks if tol is not None else 0,
+                   graph=graph, P=P, confirm=confirm)
     if info.failure is None or not fallback:
         return x, info
-    x, plain = cgls(op, g, iters, tol, check_every, graph=graph)
+    x, plain = cgls(op, g, iters, tol, check_every, graph=graph, confirm=confirm)
     plain.fallback = True
     plain.failure = info.failure
     plain.seconds += info.seconds

@@ -45,13 +45,17 @@ def test_trained_preconditioner_beats_plain_cgls(env):
     xc, ic = solvers.cgls(op, g, 1000, tol=1e-3, check_every=1)
     xp, ip = solvers.pcgls(op, P, g, 1000, tol=1e-3, check_every=1)
     assert ic.converged and ip.converged and not ip.fallback
+    # the solvers stop only once the true residual (GPU transform, FP64 norms) is <= 1e-3
+    assert ic.true_residual[-1] <= 1e-3 and ip.true_residual[-1] <= 1e-3
     # the trained network needs far fewer iterations (83 -> 49 on the 64-phantom set)
     assert ip.iterations <= 0.75 * ic.iterations, (ip.iterations, ic.iterations)
     gn = g.cpu().numpy().astype(np.float64)
     rc = _fp64_residuals(env["cfg"], xc.cpu().numpy(), gn)
     rp = _fp64_residuals(env["cfg"], xp.cpu().numpy(), gn)
-    # the FP64 data residual of both final images confirms the FP32 recursive residual
-    assert rc.max() <= 1.1e-3 and rp.max() <= 1.1e-3, (rc.max(), rp.max())
+    # the FP64 data residual of the oracle confirms both final images at the tolerance
+    assert rc.max() <= 1e-3 and rp.max() <= 1e-3, (rc.max(), rp.max())
+    # the recursion tracks the returned image: the accumulated f = sum alpha P p, not P z
+    np.testing.assert_allclose(rp.max(), ip.true_residual[-1], rtol=1e-3)
 
 
 class _Broken:
