@@ -87,9 +87,14 @@ def cpu_baseline(cfg, img, views_every: int):
     ocore.adjoint_lines(cfg["grid"], p, th, g, nthreads=threads)
     t2 = time.perf_counter()
     m = p.shape[0]
+    nv = len(cfg["scan"]["angles"])
     return {"value": m / (t2 - t0) / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {views_every}th view ({scan['angles'].size} of {len(cfg['scan']['angles'])} views, "
-                      f"{m} rays), forward {t1 - t0:.2f} s + adjoint {t2 - t1:.2f} s, FP64"}
+            "host": ocore.host_info(),
+            "sample": f"every {views_every}th view ({scan['angles'].size} of {nv} views, {m} rays; every view "
+                      f"has the same work, so the rate is that of the full scan, which would take about "
+                      f"{(t2 - t0) * nv / scan['angles'].size:.0f} s), forward {t1 - t0:.2f} s + adjoint "
+                      f"{t2 - t1:.2f} s, FP64, {threads} threads (the cores this process may use, capped by "
+                      f"OMP_NUM_THREADS)"}
 
 
 def learned_solve(torch, dev, tol: float = 1e-3):
@@ -128,6 +133,7 @@ def learned_solve(torch, dev, tol: float = 1e-3):
             "pcgls_s": round(r["pcgls"]["seconds"], 5), "pcgls_iterations": r["pcgls"]["iterations"],
             "speedup": round(r["speedup"], 3), "fallback": r["pcgls"]["fallback"],
             "true_residual": {"cgls": true_residual(xc), "pcgls": true_residual(xp)},
+            "confirmations": {"cgls": r["cgls"]["confirmations"], "pcgls": r["pcgls"]["confirmations"]},
             "weights": os.path.relpath(learned.default_weights(), ROOT), "stored_matrix": stored}
 
 
@@ -232,7 +238,8 @@ def main():
                     help="skip the forward launch-shape autotuner (untimed; default on) and keep the plan's own shape")
     ap.add_argument("--launch", default=None, metavar="PC,XR",
                     help="forward launch shape packet_cols,xcd_remap to use instead of the autotuner's")
-    ap.add_argument("--cpu-views-every", type=int, default=15)
+    ap.add_argument("--cpu-views-every", type=int, default=4,
+                    help="time the oracle on every n-th view of the scan (default 4: 90 views, about 10-15 s)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
