@@ -177,6 +177,18 @@ xrt_status xrt_ray_hits(xrt_plan* plan, int64_t first, int64_t n, double eps,
 xrt_status xrt_vec_dot(int64_t n, int32_t batch, const float* d_a, const float* d_b, double* d_work,
                        double* d_out, void* stream);
 
+/* xrt_vec_dot for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and the same result
+ * bit for bit, with the partial sums in a static device array of the library instead of
+ * a workspace argument (64 * 1024 doubles, 512 KiB, held by every GPU the library runs
+ * on until the process ends).  The kernels run on the device of `stream` (the current
+ * device for NULL); the first call on a device looks up that device's copy of the array
+ * (no allocation, no GPU work).  batch <= 1024 (XRT_E_SIZE beyond).  Every call on one
+ * GPU shares the array, so calls that overlap on one GPU (different streams without
+ * ordering between them) race; calls ordered on one stream do not. */
+xrt_status xrt_vec_dot_noalloc(int64_t n, int32_t batch, const float* d_a, const float* d_b, double* d_out,
+                               void* stream);
+
 /* d_y[b] += sign * (d_num[b] / d_den[b]) * d_x[b]; a zero denominator adds nothing. */
 xrt_status xrt_vec_axpy_ratio(int64_t n, int32_t batch, const double* d_num, const double* d_den, double sign,
                               const float* d_x, float* d_y, void* stream);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "xrt_internal.h"
 
@@ -89,6 +91,54 @@ __global__ __launch_bounds__(kVBlock) void k_transmission(float* w, const float*
         w[i] = expf(-x[i]);
 }
 
+// Partial sums of the allocation-free dot product: a file-scope device array (each GPU
+// the library runs on holds its own copy, at its own address, until the process ends).
+// Host code never names it as a kernel argument: kernels get the per-device address that
+// hipGetSymbolAddress returns (scratch_on).
+constexpr int32_t kNoAllocBatch = 1024;
+static __device__ __align__(256) double scratch[kDotBlocks * kNoAllocBatch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<double*> g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on device dev, looked up once per device with that device
+// current.
+xrt_status scratch_on(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d outside the %d devices the static scratch supports", dev, kMaxDevices);
+        return XRT_E_ARG;
+    }
+    double* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_addr[dev].load(std::memory_order_relaxed);
+        if (p == nullptr) {
+            DeviceGuard guard(dev);
+            if (!guard.ok) return hip_fail(hipErrorInvalidDevice, "hipSetDevice for the static scratch");
+            void* addr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || addr == nullptr)
+                return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress of the static scratch");
+            p = static_cast<double*>(addr);
+            g_scratch_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return XRT_OK;
+}
+
+// The two kernels of a batched dot product: 64 partial sums per member into work, then
+// their fixed-order sum into out.
+xrt_status launch_dot(int64_t n, int32_t batch, const float* a, const float* b, double* work, double* out,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, (unsigned)batch), dim3(kVBlock), 0, s, a, b, n, work);
+    hipLaunchKernelGGL(k_dot_final, dim3((unsigned)batch), dim3(kDotBlocks), 0, s, (const double*)work, out);
+    return hip_fail(hipGetLastError(), "dot product launch");
+}
+
 }  // namespace
 
 xrt_status launch_transmission(float* w, const float* x, int64_t n, hipStream_t s)
@@ -111,10 +161,30 @@ xrt_status xrt_vec_dot(int64_t n, int32_t batch, const float* d_a, const float* 
         set_error("xrt_vec_dot: bad argument");
         return XRT_E_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, (unsigned)batch), dim3(kVBlock), 0, s, d_a, d_b, n, d_work);
-    hipLaunchKernelGGL(k_dot_final, dim3((unsigned)batch), dim3(kDotBlocks), 0, s, (const double*)d_work, d_out);
-    return hip_fail(hipGetLastError(), "xrt_vec_dot launch");
+    return launch_dot(n, batch, d_a, d_b, d_work, d_out, (hipStream_t)stream);
+}
+
+xrt_status xrt_vec_dot_noalloc(int64_t n, int32_t batch, const float* d_a, const float* d_b, double* d_out,
+                               void* stream)
+{
+    if (!d_a || !d_b || !d_out || n < 1 || batch < 1) {
+        set_error("xrt_vec_dot_noalloc: bad argument");
+        return XRT_E_ARG;
+    }
+    if (batch > kNoAllocBatch) {
+        set_error("xrt_vec_dot_noalloc: batch %d exceeds the %d members of the static scratch", batch,
+                  kNoAllocBatch);
+        return XRT_E_SIZE;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    int dev = -1;
+    const hipError_t e = s != nullptr ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "xrt_vec_dot_noalloc: device of the stream");
+    double* work = nullptr;
+    const xrt_status st = scratch_on(dev, &work);
+    if (st != XRT_OK) return st;
+    DeviceGuard guard(dev);
+    return launch_dot(n, batch, d_a, d_b, work, d_out, s);
 }
 
 xrt_status xrt_vec_axpy_ratio(int64_t n, int32_t batch, const double* d_num, const double* d_den, double sign,

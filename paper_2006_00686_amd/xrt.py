@@ -73,6 +73,7 @@ def _lib():
         lib.xrt_status_str.restype = ctypes.c_char_p
         lib.xrt_last_error.restype = ctypes.c_char_p
         lib.xrt_vec_dot.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+        lib.xrt_vec_dot_noalloc.argtypes = [i64, i32, vp, vp, vp, vp]
         lib.xrt_vec_axpy_ratio.argtypes = [i64, i32, vp, vp, ctypes.c_double, vp, vp, vp]
         lib.xrt_vec_xpby_ratio.argtypes = [i64, i32, vp, vp, vp, vp, vp]
         lib.xrt_vec_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
@@ -453,6 +454,18 @@ def vec_dot(a: torch.Tensor, b: torch.Tensor, batch: int, work: torch.Tensor, ou
     n = _vec_args(a, batch)
     _check(_lib().xrt_vec_dot(n, batch, _ptr(a), _ptr(b), _ptr(work), _ptr(out), _stream(a.device.index)),
            "xrt_vec_dot")
+    return out
+
+
+def vec_dot_noalloc(a: torch.Tensor, b: torch.Tensor, batch: int, out: torch.Tensor):
+    """out[k] = <a[k], b[k]> (FP64) like vec_dot, with the library's static scratch instead of
+    a workspace (no allocation)."""
+    n = _vec_args(a, batch)
+    if (_vec_args(b, batch) != n or a.numel() != n * batch or b.numel() != n * batch
+            or out.dtype != torch.float64 or not out.is_contiguous() or out.numel() < batch):
+        raise ValueError("vec_dot_noalloc: shape or dtype mismatch")
+    _check(_lib().xrt_vec_dot_noalloc(n, batch, _ptr(a), _ptr(b), _ptr(out), _stream(a.device.index)),
+           "xrt_vec_dot_noalloc")
     return out
 
 
