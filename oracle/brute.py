@@ -115,3 +115,56 @@ def one_unit_lengths(g: dict, P, TH, unit):
         inside = (lo <= P[:, a]) & (P[:, a] < hi) if sgn > 0 else (lo < P[:, a]) & (P[:, a] <= hi)
         member &= mv | inside
     return np.where(member, np.maximum(U - L, 0.0), 0.0)
+
+
+# ------------------------------------------------------------------ simplex basis
+# Simplex s of a unit is the set of points whose local index coordinates (in [0, 1] per
+# axis), sorted from largest to smallest, come in the s-th axis order below (Kuhn's
+# triangulation of the pixel / voxel in index coordinates).
+SIMPLEX_ORDERS = {2: [(0, 1), (1, 0)],
+                  3: [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]}
+
+
+def _index_line(g: dict, p, th):
+    """Index coordinates of the line: xi(t) = x0 + t om, t the physical arc length
+    (x: (x - cx)/dx + nx/2; y: ny/2 - (y - cy)/dy; z: nz/2 - (z - cz)/dz)."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    th = np.asarray(th, dtype=np.float64).ravel()
+    d3 = int(g.get("nz", 0)) > 0
+    axes = [("nx", "dx", "cx", +1), ("ny", "dy", "cy", -1)] + ([("nz", "dz", "cz", -1)] if d3 else [])
+    x0, om = [], []
+    for a, (kn, kd, kc, sgn) in enumerate(axes):
+        d, c, n = float(g.get(kd, 1.0)), float(g.get(kc, 0.0)), int(g[kn])
+        x0.append(sgn * (p[a] - c) / d + n / 2.0)
+        om.append(sgn * th[a] / d)
+    return np.array(x0), np.array(om)
+
+
+def simplex_lengths(g: dict, p, th):
+    """Dense array (image shape + (S,)) of len(ray, simplex) for every simplex: the line
+    clipped against the simplex's half-spaces (closed), one simplex at a time."""
+    x0, om = _index_line(g, p, th)
+    dim = x0.size
+    shape = tuple(int(g[k]) for k in (["nz"] if dim == 3 else []) + ["ny", "nx"])
+    orders = SIMPLEX_ORDERS[dim]
+    out = np.zeros(shape + (len(orders),))
+    for unit in np.ndindex(*shape):
+        base = np.array(unit[::-1], dtype=np.float64)          # (i, j[, k]) along x, y[, z]
+        a0 = x0 - base                                          # local coordinates at t = 0
+        for s, order in enumerate(orders):
+            # constraints alpha + beta t >= 0: l_first <= 1, l_o[m] >= l_o[m+1], l_last >= 0
+            cons = [(1.0 - a0[order[0]], -om[order[0]])]
+            for m in range(dim - 1):
+                u, v = order[m], order[m + 1]
+                cons.append((a0[u] - a0[v], om[u] - om[v]))
+            cons.append((a0[order[-1]], om[order[-1]]))
+            lo, hi = -np.inf, np.inf
+            for alpha, beta in cons:
+                if beta > 0.0:
+                    lo = max(lo, -alpha / beta)
+                elif beta < 0.0:
+                    hi = min(hi, -alpha / beta)
+                elif alpha < 0.0:
+                    hi = -np.inf
+            out[unit + (s,)] = max(0.0, hi - lo)
+    return out

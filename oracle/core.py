@@ -52,6 +52,10 @@ def _load():
         lib.ora_hit_counts.argtypes = [gp, ctypes.c_long, dp, dp, ctypes.c_double, lp, ctypes.c_int]
         lib.ora_forward_att.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.ora_adjoint_att.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, dp, ctypes.c_int]
+        lib.ora_forward_simplex.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, ctypes.c_int]
+        lib.ora_adjoint_simplex.argtypes = [gp, ctypes.c_long, dp, dp, dp, dp, ctypes.c_int]
+        lib.ora_ray_hits_simplex.argtypes = [gp, dp, dp, lp, dp, ctypes.c_long, ctypes.c_double]
+        lib.ora_ray_hits_simplex.restype = ctypes.c_long
         lib.ora_chord.argtypes = [gp, dp, dp]
         lib.ora_chord.restype = ctypes.c_double
         _lib = lib
@@ -247,3 +251,53 @@ def adjoint(g: dict, scan: dict, sino, nthreads=None):
 def hit_counts(g: dict, scan: dict, eps=0.0, nthreads=None):
     p, th = geometry.expand(scan)
     return hit_counts_lines(g, p, th, eps, nthreads).reshape(geometry.sino_shape(scan))
+
+
+# ------------------------------------------------------------------ simplex basis
+
+def simplex_count(g: dict) -> int:
+    """Simplices per unit: 2 triangles per pixel, 6 tetrahedra per voxel."""
+    return 6 if int(g.get("nz", 0)) > 0 else 2
+
+
+def simplex_image_shape(g: dict):
+    return tuple(image_shape(g)) + (simplex_count(g),)
+
+
+def forward_simplex_lines(g: dict, p, th, img, nthreads=None):
+    """X-ray transform of an image on the simplices of the structured triangulation
+    (every pixel cut into 2 triangles, every voxel into 6 tetrahedra; the definition is
+    in xrt_oracle.c): out[r] = sum_T img[T] len(r, T)."""
+    lib = _load()
+    p, th = _c(p).reshape(-1, 3), _c(th).reshape(-1, 3)
+    img = _c(img)
+    out = np.zeros(p.shape[0], dtype=np.float64)
+    gg = _grid(g)
+    lib.ora_forward_simplex(ctypes.byref(gg), p.shape[0], _dptr(p), _dptr(th), _dptr(img), _dptr(out),
+                            nthreads or default_threads())
+    return out
+
+
+def adjoint_simplex_lines(g: dict, p, th, sino, nthreads=None):
+    lib = _load()
+    p, th = _c(p).reshape(-1, 3), _c(th).reshape(-1, 3)
+    sino = _c(sino).ravel()
+    img = np.zeros(int(np.prod(simplex_image_shape(g))), dtype=np.float64)
+    gg = _grid(g)
+    lib.ora_adjoint_simplex(ctypes.byref(gg), p.shape[0], _dptr(p), _dptr(th), _dptr(sino), _dptr(img),
+                            nthreads or default_threads())
+    return img.reshape(simplex_image_shape(g))
+
+
+def ray_hits_simplex_line(g: dict, p, th, eps=0.0):
+    """(simplex indices, lengths) of one ray, sorted by index; lengths > eps."""
+    lib = _load()
+    p, th = _c(p).ravel(), _c(th).ravel()
+    cap = 3 * (int(g["nx"]) + int(g["ny"]) + int(g.get("nz", 0))) + 16
+    idx = np.zeros(cap, dtype=np.int64)
+    ln = np.zeros(cap, dtype=np.float64)
+    gg = _grid(g)
+    n = lib.ora_ray_hits_simplex(ctypes.byref(gg), _dptr(p), _dptr(th),
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dptr(ln), cap, eps)
+    n = min(n, cap)
+    return idx[:n].copy(), ln[:n].copy()

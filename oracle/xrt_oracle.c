@@ -390,3 +390,217 @@ void ora_adjoint_att(const ora_grid* g, long nrays, const double* p, const doubl
     free(part);
 }
 
+
+/* ---------------------------------------------------------------- simplex basis
+ * The image on the simplices of a structured triangulation (the paper's polygonal /
+ * polyhedral extension, Introduction "Contributions" and Sec. 4.2): in index
+ * coordinates xi (xi_a = its floor is the unit index along axis a) every pixel is cut
+ * into 2 triangles by the plane xi_x - xi_y = const, every voxel into 6 tetrahedra by the
+ * planes xi_x - xi_y, xi_y - xi_z, xi_x - xi_z = const (Kuhn's triangulation).  Simplex
+ * s of unit I is the set of points whose local coordinates l_a = xi_a - floor(xi_a),
+ * sorted from largest to smallest, come in the s-th order of the axes in lexicographic
+ * order: 2D (x,y) = 0, (y,x) = 1; 3D (x,y,z) = 0, (x,z,y) = 1, (y,x,z) = 2,
+ * (y,z,x) = 3, (z,x,y) = 4, (z,y,x) = 5.  Equal coordinates rank the later axis first,
+ * which gives a point on a diagonal plane to the simplex with the bigger index (the
+ * resolution of Sec. 4.1 carried to the new faces).  Simplex index = I * S + s, S = 2 (2D)
+ * or 6 (3D).
+ *
+ * Method: the chord partition again, with the crossings of the diagonal plane families
+ * xi_a - xi_b = integer added to those of the grid planes; each piece goes to the
+ * simplex containing its midpoint. */
+
+static long simplex_count(const ogrid* o) { return o->dim == 3 ? 6 : 2; }
+
+static long max_crossings_simplex(const ogrid* o)
+{
+    return 3L * ((long)o->n[0] + o->n[1] + o->n[2]) + 16;
+}
+
+/* index coordinate of axis a along the ray: xi_a(t) = x0[a] + t * om[a] */
+static void index_line(const ogrid* o, const double* pu, const double* wu, double* x0, double* om)
+{
+    for (int a = 0; a < 3; ++a) { x0[a] = 0.0; om[a] = 0.0; }
+    for (int a = 0; a < o->dim; ++a) {
+        x0[a] = index_coord(o, a, pu[a]);
+        om[a] = a == 0 ? wu[a] : -wu[a];
+    }
+}
+
+/* rank of the permutation that sorts the local coordinates (largest first, ties: the
+ * later axis first), lexicographic over permutations */
+static int simplex_of(int dim, const double* l)
+{
+    if (dim == 2) return (l[1] >= l[0]) ? 1 : 0;
+    int ord[3] = {0, 1, 2};
+    /* insertion sort by "ranks before": value larger, or equal and axis later */
+    for (int i = 1; i < 3; ++i) {
+        int k = ord[i], j = i - 1;
+        while (j >= 0 && (l[k] > l[ord[j]] || (l[k] == l[ord[j]] && k > ord[j]))) {
+            ord[j + 1] = ord[j];
+            --j;
+        }
+        ord[j + 1] = k;
+    }
+    static const int rank[3][3] = {{-1, 0, 1}, {2, -1, 3}, {4, 5, -1}};  /* [first][second] */
+    return rank[ord[0]][ord[1]];
+}
+
+static void simplex_walk(const ogrid* o, const double* p, const double* th, double* buf,
+                         visit_fn fn, void* ctx)
+{
+    double pu[3], wu[3], tin, tout, x0[3], om[3];
+    to_unit(o, p, th, pu, wu);
+    if (!clip(o, pu, wu, &tin, &tout)) return;
+    index_line(o, pu, wu, x0, om);
+    long m = 0;
+    /* grid planes xi_a = integer */
+    for (int a = 0; a < o->dim; ++a) {
+        if (om[a] == 0.0) continue;
+        for (int q = 1; q < o->n[a]; ++q) {
+            double t = ((double)q - x0[a]) / om[a];
+            if (t > tin && t < tout) buf[m++] = t;
+        }
+    }
+    /* diagonal planes xi_a - xi_b = integer */
+    static const int pairs[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+    int npairs = o->dim == 3 ? 3 : 1;
+    for (int k = 0; k < npairs; ++k) {
+        int a = pairs[k][0], b = pairs[k][1];
+        double d0 = x0[a] - x0[b], dw = om[a] - om[b];
+        if (dw == 0.0) continue;
+        double e0 = d0 + tin * dw, e1 = d0 + tout * dw;
+        double lo = fmin(e0, e1), hi = fmax(e0, e1);
+        for (double q = ceil(lo); q <= floor(hi); q += 1.0) {
+            double t = (q - d0) / dw;
+            if (t > tin && t < tout) buf[m++] = t;
+        }
+    }
+    qsort(buf, (size_t)m, sizeof(double), cmp_double);
+    long S = simplex_count(o);
+    double prev = tin;
+    for (long s = 0; s <= m; ++s) {
+        double next = s < m ? buf[s] : tout;
+        if (next > prev) {
+            double mid = 0.5 * (prev + next);
+            long idx[3] = {0, 0, 0};
+            double loc[3] = {0.0, 0.0, 0.0};
+            int ok = 1;
+            for (int a = 0; a < o->dim; ++a) {
+                double q = x0[a] + mid * om[a];
+                double f = floor(q);
+                if (f < 0.0 || f >= (double)o->n[a]) { ok = 0; break; }
+                idx[a] = (long)f;
+                loc[a] = q - f;
+            }
+            if (ok) {
+                long I = (idx[2] * o->n[1] + idx[1]) * (long)o->n[0] + idx[0];
+                fn(ctx, I * S + simplex_of(o->dim, loc), next - prev);
+            }
+        }
+        prev = next;
+    }
+}
+
+void ora_forward_simplex(const ora_grid* g, long nrays, const double* p, const double* th,
+                         const double* img, double* out, int nthreads)
+{
+    ogrid o;
+    make_grid(g, &o);
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        double* buf = (double*)malloc(sizeof(double) * (size_t)max_crossings_simplex(&o));
+#pragma omp for schedule(dynamic, 64)
+        for (long r = 0; r < nrays; ++r) {
+            fwd_ctx c = {img, 0.0};
+            simplex_walk(&o, p + 3 * r, th + 3 * r, buf, fwd_visit, &c);
+            out[r] = c.acc;
+        }
+        free(buf);
+    }
+}
+
+void ora_adjoint_simplex(const ora_grid* g, long nrays, const double* p, const double* th,
+                         const double* sino, double* img, int nthreads)
+{
+    ogrid o;
+    make_grid(g, &o);
+    long nv = n_units(&o) * simplex_count(&o);
+    if (nthreads < 1) nthreads = 1;
+    double* part = (double*)calloc((size_t)nthreads * (size_t)nv, sizeof(double));
+#pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* mine = part + (size_t)tid * (size_t)nv;
+        double* buf = (double*)malloc(sizeof(double) * (size_t)max_crossings_simplex(&o));
+#pragma omp for schedule(static)
+        for (long r = 0; r < nrays; ++r) {
+            if (sino[r] == 0.0) continue;
+            adj_ctx c = {mine, sino[r]};
+            simplex_walk(&o, p + 3 * r, th + 3 * r, buf, adj_visit, &c);
+        }
+        free(buf);
+    }
+    memset(img, 0, sizeof(double) * (size_t)nv);
+    for (int t = 0; t < nthreads; ++t) {
+        const double* src = part + (size_t)t * (size_t)nv;
+        for (long I = 0; I < nv; ++I) img[I] += src[I];
+    }
+    free(part);
+}
+
+/* consecutive pieces of one simplex (split by a crossing that rounding placed inside
+ * it) count as one hit */
+typedef struct { long* idx; double* len; long n, cap; long last; double run; double eps; } shit_ctx;
+
+static void shit_flush(shit_ctx* h)
+{
+    if (h->last >= 0 && h->run > h->eps) {
+        if (h->n < h->cap) {
+            h->idx[h->n] = h->last;
+            h->len[h->n] = h->run;
+        }
+        h->n++;
+    }
+}
+
+static void shit_visit(void* c, long I, double len)
+{
+    shit_ctx* h = (shit_ctx*)c;
+    if (I == h->last) {
+        h->run += len;
+        return;
+    }
+    shit_flush(h);
+    h->last = I;
+    h->run = len;
+}
+
+long ora_ray_hits_simplex(const ora_grid* g, const double* p, const double* th,
+                          long* idx, double* len, long cap, double eps)
+{
+    ogrid o;
+    make_grid(g, &o);
+    double* buf = (double*)malloc(sizeof(double) * (size_t)max_crossings_simplex(&o));
+    shit_ctx h = {idx, len, 0, cap, -1, 0.0, eps};
+    simplex_walk(&o, p, th, buf, shit_visit, &h);
+    shit_flush(&h);
+    free(buf);
+    long n = h.n < cap ? h.n : cap;
+    for (long a = 1; a < n; ++a) {
+        long ki = idx[a];
+        double kl = len[a];
+        long b = a - 1;
+        while (b >= 0 && idx[b] > ki) {
+            idx[b + 1] = idx[b];
+            len[b + 1] = len[b];
+            --b;
+        }
+        idx[b + 1] = ki;
+        len[b + 1] = kl;
+    }
+    return h.n;
+}

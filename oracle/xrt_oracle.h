@@ -72,6 +72,18 @@ void ora_forward_att(const ora_grid* g, long nrays, const double* p, const doubl
 void ora_adjoint_att(const ora_grid* g, long nrays, const double* p, const double* th,
                      const double* sino, const double* mu, double* img, int nthreads);
 
+/* Simplex basis (the paper's polygonal / polyhedral extension; Introduction
+ * "Contributions", Sec. 4.2): every pixel cut into 2 triangles, every voxel into 6
+ * tetrahedra (Kuhn's triangulation in index coordinates; the definition is stated in
+ * xrt_oracle.c).  Images hold S = 2 (2D) or 6 (3D) values per unit, simplex index
+ * I * S + s.  Forward, adjoint and hit lists as above, over simplices. */
+void ora_forward_simplex(const ora_grid* g, long nrays, const double* p, const double* th,
+                         const double* img, double* out, int nthreads);
+void ora_adjoint_simplex(const ora_grid* g, long nrays, const double* p, const double* th,
+                         const double* sino, double* img, int nthreads);
+long ora_ray_hits_simplex(const ora_grid* g, const double* p, const double* th,
+                          long* idx, double* len, long cap, double eps);
+
 #ifdef __cplusplus
 }
 #endif
