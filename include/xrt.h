@@ -259,6 +259,24 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
 xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,
                                   float* d_img, int32_t batch, void* stream);
 
+/* The transform on a simplex basis (the paper's polygonal / polyhedral extension:
+ * Introduction "Contributions", Sec. 4.2).  The image lives on the simplices of a
+ * structured triangulation of the plan's grid: in index coordinates (unit (k,j,i) =
+ * [i,i+1) x [j,j+1) x [k,k+1)) every pixel is cut into 2 triangles by the plane
+ * x - y = const, every voxel into 6 tetrahedra by the planes x - y, y - z, x - z = const.
+ * Simplex s of a unit holds the points whose local coordinates, sorted largest first,
+ * come in the s-th axis order: 2D (x,y) = 0, (y,x) = 1; 3D (x,y,z) = 0, (x,z,y) = 1,
+ * (y,x,z) = 2, (y,z,x) = 3, (z,x,y) = 4, (z,y,x) = 5; equal coordinates rank the later
+ * axis first, so a ray inside a diagonal face is given to the simplex with the bigger
+ * index (Sec. 4.1's resolution carried to the new faces).  d_img: float32
+ * [batch][nz][ny][nx][S] ([batch][ny][nx][2] in 2D), S = 6 (3D) or 2 (2D), i.e. simplex
+ * index I * S + s.  A simplex is hit iff C_low < C_up over its facets, len = C_up - C_low.
+ * Forward: d_sino[b][r] = sum_T d_img[b][T] len(r, T), overwriting d_sino.  Adjoint: its
+ * transpose, ray-driven with float atomics (summation order not fixed), overwriting d_img.
+ * Every ray kind of the plan; same sinogram layout and errors as xrt_forward. */
+xrt_status xrt_forward_simplex(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* stream);
+xrt_status xrt_adjoint_simplex(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* stream);
+
 /* Per-ray weighted transform (Introduction, eq. generalizedRadontransform, PET case: the
  * weight does not depend on the position along the ray, so the generalised transform is
  * the X-ray transform times a weight given per ray).  d_w: float32 weights in sinogram
@@ -311,7 +329,7 @@ xrt_status xrt_plan_get_tuning(const xrt_plan* plan, xrt_tuning* tuning);
  * exists; their launch shapes are taken at creation.  The forward of all members is one
  * persistent kernel whose workgroups draw chunks of rays from a queue ordered by ray
  * length (longest first), after one small reset kernel (and the y-fastest copies of
- * the images of 3D plans that use them); no allocation, copy or host synchronisation
+ * the images of plans that use them); no allocation, copy or host synchronisation
  * happens in xrt_batch_forward / xrt_batch_adjoint, so both can be captured in a graph.
  * The rays of one member match xrt_forward of its plan bit for bit.  Host arrays of n
  * device pointers: images [nz][ny][nx] and sinograms of each member. */

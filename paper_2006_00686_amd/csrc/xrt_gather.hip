@@ -65,8 +65,8 @@ __device__ __forceinline__ int32_t iceil(double x, int32_t hi)
     return (int32_t)ceil(fmin(fmax(x, -1.0), (double)hi));
 }
 
-// 1/x: hardware estimate refined by one Newton step (full FP64 precision for the
-// lengths; the ranges below only need the estimate).
+// 1/x: the hardware estimate (relative error below 2^-20; 2^-24.4 measured on gfx950),
+// and that estimate refined by one Newton step (error squared: full FP64 precision).
 __device__ __forceinline__ double rcp_fast(double x)
 {
     return __builtin_amdgcn_rcp(x);
@@ -105,7 +105,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64
 }
 
 constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
-constexpr double kRangeSlack = 1e-7;   // widening of candidate ranges (in bins)
+// widening of candidate row ranges (in bins); column ranges, which come from the
+// hardware reciprocal's estimate (relative error below 2^-20; 2^-24.4 measured on gfx950),
+// are widened by the plan's uslack instead
+constexpr double kRangeSlack = 1e-7;
 
 // The rays of one (view, detector column) that can cross a wave's pixel column, as
 // every lane of the wave needs them: the pixel's xy interval (tin, tout) of the ray
@@ -198,8 +201,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 umin = fmin(umin, u);
                 umax = fmax(umax, u);
             }
-            const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
-            const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
+            const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
+            const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
             const int32_t cb = c0 + (pass << lg_slots);
             if (__builtin_amdgcn_ballot_w64(vok && cb <= c1) == 0) break;
             // C_low / C_up of the pixel in xy, shared by every ray of column c
@@ -218,8 +221,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
                 R.tin[at] = tin;
                 R.tout[at] = tout;
-                R.sin[at] = rcp_fast(tin) * idv;
-                R.sout[at] = rcp_fast(tout) * idv;
+                // 1/tau in row bins for the candidate rows: refined, so that a row range of
+                // a few hundred bins stays within the rows' 1e-7-bin slack
+                R.sin[at] = rcp_full(tin) * idv;
+                R.sout[at] = rcp_full(tout) * idv;
                 R.sz[at] = V.A[2];
                 R.g[at] = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
                 if constexpr (CULL && KB == 4) {
@@ -348,40 +353,76 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 }
 
 // ---------------------------------------------------------------------------------
-// 2D gather adjoint (every 2D scan kind): one lane per pixel, BB images per lane.  Per
-// view the pixel's shadow on the detector gives the candidate bins; each candidate ray
-// is clipped against the pixel (C_low < C_up of eq. conditions_2D_1, half-open faces)
-// and adds g * len.  Deterministic: fixed view and bin order.
+// 2D gather adjoint (every 2D scan kind): one lane per pixel, BB images per lane, and
+// the views split over the kG2Waves waves of a block (wave w takes views w, w + kG2Waves,
+// ...), whose sums are added in wave order at the end (deterministic: fixed view, bin
+// and wave order).  Per view the pixel's shadow on the detector gives the candidate
+// bins; each candidate ray is clipped against the pixel (C_low < C_up of eq.
+// conditions_2D_1, half-open faces) and adds g * len.
+//
+// The clip takes the ray parameter in physical length: with J = |d| / d per axis (the
+// plan's ray2d table, 0 for a zero component), the pixel's x interval is
+// (x - o_x) J_x over x in {xa, xb}, so len = C_up - C_low directly.  Every candidate's
+// work is four products, six min / max and one multiply-add per image.
 // wt: per-ray weights applied to the sinogram values (the PET form), or none.
-template <int MODE, int BB>
-__global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __restrict__ sino,
-                                                      float* __restrict__ img, int32_t batch,
-                                                      const float* __restrict__ wt, int64_t wt_stride)
+constexpr int kG2Waves = 4;
+
+// C_up - C_low of the ray with origin offsets a0 = xa - o_x, a1 = xb - o_x, b0 = ya - o_y,
+// b1 = yb - o_y and J (0: the ray runs along that axis's grid lines, where the pixel
+// owns x in [xa, xb) and y in (ya, yb])
+__device__ __forceinline__ double clip2d(double a0, double a1, double b0, double b1, double jx, double jy)
 {
-    const int32_t pix = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (pix >= P.nx * P.ny) return;
+    double lo = -kInf, hi = kInf;
+    if (jx != 0.0) {
+        const double t0 = a0 * jx, t1 = a1 * jx;
+        lo = fmin(t0, t1);
+        hi = fmax(t0, t1);
+    } else if (!(a0 <= 0.0 && a1 > 0.0)) {
+        hi = -kInf;
+    }
+    if (jy != 0.0) {
+        const double t0 = b0 * jy, t1 = b1 * jy;
+        lo = fmax(lo, fmin(t0, t1));
+        hi = fmin(hi, fmax(t0, t1));
+    } else if (!(b0 < 0.0 && b1 >= 0.0)) {
+        hi = -kInf;
+    }
+    return hi - lo;
+}
+
+template <int MODE, int BB>
+__global__ __launch_bounds__(64 * kG2Waves) void k_gather2d(DevPlan P, const float* __restrict__ sino,
+                                                             float* __restrict__ img, int32_t batch,
+                                                             const float* __restrict__ wt, int64_t wt_stride)
+{
+    __shared__ double part[kG2Waves - 1][BB][64];
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t pix = (int32_t)blockIdx.x * 64 + lane;
+    const bool live = pix < P.nx * P.ny;
     const int32_t b0 = blockIdx.y * BB;
-    const int32_t i = pix % P.nx, j = pix / P.nx;
+    const int32_t i = live ? pix % P.nx : 0, j = live ? pix / P.nx : 0;
     const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double idu = 1.0 / P.du;
     double acc[BB];
 #pragma unroll
     for (int q = 0; q < BB; ++q) acc[q] = 0.0;
-    for (int32_t v = 0; v < P.n_views; ++v) {
+    for (int32_t v = wv; v < P.n_views && live; v += kG2Waves) {
         const ViewGeom& V = P.views[v];
         const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
-        // detector coordinate of the four corners
+        // corner offsets from the view's origin (the source for rays that fan out)
+        const double a0 = xa - Ax, a1 = xb - Ax, c0y = ya - Ay, c1y = yb - Ay;
+        // detector coordinate of the four corners: the candidate bins (hits and lengths
+        // come from the exact clip; the range's slack covers the reciprocal's rounding)
         double umin = kInf, umax = -kInf;
 #pragma unroll
         for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = ((cnr & 1) ? xb : xa) - Ax, py = ((cnr & 2) ? yb : ya) - Ay;
+            const double px = (cnr & 1) ? a1 : a0, py = (cnr & 2) ? c1y : c0y;
             double u;
             if constexpr (MODE == MODE_PARALLEL) {
                 u = fma(px, Bx, py * By);                        // p = u B (+ t E)
             } else if constexpr (MODE == MODE_DIVERGENT) {
-                // candidate range only (hits and lengths come from the exact clip below;
-                // the range's slack covers the hardware reciprocal's rounding)
                 const double e2 = Ex * Ex + Ey * Ey;             // |E|^2 = sdd^2
                 u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
             } else {
@@ -390,62 +431,68 @@ __global__ __launch_bounds__(kBlock) void k_gather2d(DevPlan P, const float* __r
             umin = fmin(umin, u);
             umax = fmax(umax, u);
         }
-        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
-        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
-        for (int32_t c = c0; c <= c1; ++c) {
-            const double u = fma((double)c, P.du, P.ubase);
-            double sx, sy, dx, dy;
+        const int32_t cb = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
+        const int32_t ce = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
+        double jx = 0.0, jy = 0.0;
+        if constexpr (MODE == MODE_PARALLEL) {
+            jx = P.ray2d[2 * v];
+            jy = P.ray2d[2 * v + 1];
+        }
+        for (int32_t c = cb; c <= ce; ++c) {
+            double len;
             if constexpr (MODE == MODE_PARALLEL) {
-                sx = fma(u, Bx, Ax);
-                sy = fma(u, By, Ay);
-                dx = Ex;
-                dy = Ey;
-            } else if constexpr (MODE == MODE_DIVERGENT) {
-                sx = Ax;
-                sy = Ay;
-                dx = fma(u, Bx, Ex);
-                dy = fma(u, By, Ey);
+                // origin A + u B moves with the bin; the direction is the view's
+                const double u = fma((double)c, P.du, P.ubase);
+                const double ox = u * Bx, oy = u * By;
+                len = clip2d(a0 - ox, a1 - ox, c0y - oy, c1y - oy, jx, jy);
             } else {
-                const double ca = P.col_cs[2 * c], sa = P.col_cs[2 * c + 1];
-                sx = Ax;
-                sy = Ay;
-                dx = fma(ca, Ex, sa * Bx);
-                dy = fma(ca, Ey, sa * By);
+                const double2 J = *reinterpret_cast<const double2*>(P.ray2d + 2 * ((int64_t)v * P.n_cols + c));
+                len = clip2d(a0, a1, c0y, c1y, J.x, J.y);
             }
-            double tin = -kInf, tout = kInf;
-            axis_interval(xa - sx, xb - sx, dx, true, tin, tout);
-            axis_interval(ya - sy, yb - sy, dy, false, tin, tout);
-            if (!(tin < tout)) continue;
-            const double len = (tout - tin) * sqrt(dx * dx + dy * dy);   // C_up - C_low, physical
+            if (!(len > 0.0)) continue;
             const int64_t r = (int64_t)v * P.n_cols + c;
 #pragma unroll
             for (int q = 0; q < BB; ++q)
-                if (b0 + q < batch) {
+                if (BB == 1 || b0 + q < batch) {
                     double g = (double)sino[(int64_t)(b0 + q) * P.n_rays + r];
                     if (wt != nullptr) g *= (double)wt[(int64_t)(b0 + q) * wt_stride + r];
                     acc[q] = fma(g, len, acc[q]);
                 }
         }
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int q = 0; q < BB; ++q)
-        if (b0 + q < batch) img[(int64_t)(b0 + q) * P.n_units + pix] = (float)acc[q];
+        for (int q = 0; q < BB; ++q) part[wv - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (wv == 0 && live) {
+#pragma unroll
+        for (int q = 0; q < BB; ++q) {
+            double s = acc[q];
+#pragma unroll
+            for (int w = 0; w < kG2Waves - 1; ++w) s += part[w][q][lane];
+            if (BB == 1 || b0 + q < batch) img[(int64_t)(b0 + q) * P.n_units + pix] = (float)s;
+        }
+    }
 }
 
 // 2D gather adjoint of a batch of up to 64 sinograms held interleaved ([ray][image]):
-// one lane per pixel and 8 images per lane, as k_gather2d, but a candidate's 8 values are
+// one lane per pixel and 8 images per lane, as k_gather2d (same view split over the
+// block's waves, same clip, same order of every sum), but a candidate's 8 values are
 // contiguous: with VEC (batch a multiple of 4) two 16-byte loads of the group's images
-// inside the batch (a group of 4 past it is not read), else 8 guarded loads.  Each
-// (pixel, image) takes the same arithmetic in the same order as k_gather2d.
+// inside the batch (a group of 4 past it is not read), else 8 guarded loads.
 template <int MODE, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* __restrict__ sino,
-                                                         float* __restrict__ img, int32_t batch)
+__global__ __launch_bounds__(64 * kG2Waves) void k_gather2d_il(DevPlan P, const float* __restrict__ sino,
+                                                                float* __restrict__ img, int32_t batch)
 {
     constexpr int BB = 8;
-    const int32_t pix = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (pix >= P.nx * P.ny) return;
+    __shared__ double part[kG2Waves - 1][BB][64];
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t pix = (int32_t)blockIdx.x * 64 + lane;
+    const bool live = pix < P.nx * P.ny;
     const int32_t b0 = blockIdx.y * BB;
-    const int32_t i = pix % P.nx, j = pix / P.nx;
+    const int32_t i = live ? pix % P.nx : 0, j = live ? pix / P.nx : 0;
     const double xa = fma((double)i, P.pdx, P.px0), xb = xa + P.pdx;
     const double yb = P.py0 - (double)j * P.pdy, ya = yb - P.pdy;
     const double idu = 1.0 / P.du;
@@ -453,13 +500,14 @@ __global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* 
     double acc[BB];
 #pragma unroll
     for (int q = 0; q < BB; ++q) acc[q] = 0.0;
-    for (int32_t v = 0; v < P.n_views; ++v) {
+    for (int32_t v = wv; v < P.n_views && live; v += kG2Waves) {
         const ViewGeom& V = P.views[v];
         const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
+        const double a0 = xa - Ax, a1 = xb - Ax, c0y = ya - Ay, c1y = yb - Ay;
         double umin = kInf, umax = -kInf;
 #pragma unroll
         for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = ((cnr & 1) ? xb : xa) - Ax, py = ((cnr & 2) ? yb : ya) - Ay;
+            const double px = (cnr & 1) ? a1 : a0, py = (cnr & 2) ? c1y : c0y;
             double u;
             if constexpr (MODE == MODE_PARALLEL) {
                 u = fma(px, Bx, py * By);
@@ -472,33 +520,24 @@ __global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* 
             umin = fmin(umin, u);
             umax = fmax(umax, u);
         }
-        const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -kRangeSlack), P.n_cols), 0);
-        const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, kRangeSlack), P.n_cols), P.n_cols - 1);
-        for (int32_t c = c0; c <= c1; ++c) {
-            const double u = fma((double)c, P.du, P.ubase);
-            double sx, sy, dx, dy;
+        const int32_t cb = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
+        const int32_t ce = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
+        double jx = 0.0, jy = 0.0;
+        if constexpr (MODE == MODE_PARALLEL) {
+            jx = P.ray2d[2 * v];
+            jy = P.ray2d[2 * v + 1];
+        }
+        for (int32_t c = cb; c <= ce; ++c) {
+            double len;
             if constexpr (MODE == MODE_PARALLEL) {
-                sx = fma(u, Bx, Ax);
-                sy = fma(u, By, Ay);
-                dx = Ex;
-                dy = Ey;
-            } else if constexpr (MODE == MODE_DIVERGENT) {
-                sx = Ax;
-                sy = Ay;
-                dx = fma(u, Bx, Ex);
-                dy = fma(u, By, Ey);
+                const double u = fma((double)c, P.du, P.ubase);
+                const double ox = u * Bx, oy = u * By;
+                len = clip2d(a0 - ox, a1 - ox, c0y - oy, c1y - oy, jx, jy);
             } else {
-                const double ca = P.col_cs[2 * c], sa = P.col_cs[2 * c + 1];
-                sx = Ax;
-                sy = Ay;
-                dx = fma(ca, Ex, sa * Bx);
-                dy = fma(ca, Ey, sa * By);
+                const double2 J = *reinterpret_cast<const double2*>(P.ray2d + 2 * ((int64_t)v * P.n_cols + c));
+                len = clip2d(a0, a1, c0y, c1y, J.x, J.y);
             }
-            double tin = -kInf, tout = kInf;
-            axis_interval(xa - sx, xb - sx, dx, true, tin, tout);
-            axis_interval(ya - sy, yb - sy, dy, false, tin, tout);
-            if (!(tin < tout)) continue;
-            const double len = (tout - tin) * sqrt(dx * dx + dy * dy);
+            if (!(len > 0.0)) continue;
             const int64_t at = (int64_t)(v * P.n_cols + c) * batch + b0;
             float g[BB];
             if constexpr (VEC) {
@@ -514,9 +553,20 @@ __global__ __launch_bounds__(kBlock) void k_gather2d_il(DevPlan P, const float* 
             for (int q = 0; q < BB; ++q) acc[q] = fma((double)g[q], len, acc[q]);
         }
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int q = 0; q < BB; ++q)
-        if (b0 + q < batch) img[(int64_t)pix * batch + b0 + q] = (float)acc[q];
+        for (int q = 0; q < BB; ++q) part[wv - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (wv == 0 && live) {
+#pragma unroll
+        for (int q = 0; q < BB; ++q) {
+            double s = acc[q];
+#pragma unroll
+            for (int w = 0; w < kG2Waves - 1; ++w) s += part[w][q][lane];
+            if (b0 + q < batch) img[(int64_t)pix * batch + b0 + q] = (float)s;
+        }
+    }
 }
 
 template <int KB, int NR, bool CULL>
@@ -568,24 +618,22 @@ xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* 
                                    const float* wt, int64_t wt_stride)
 {
     const DevPlan& P = p->dp;
-    constexpr int BB = 8;
-    const dim3 grid((unsigned)((P.nx * P.ny + kBlock - 1) / kBlock), (unsigned)((batch + BB - 1) / BB));
+    if (P.mode != MODE_PARALLEL && P.mode != MODE_DIVERGENT && P.mode != MODE_ARC) {
+        set_error("no gather adjoint for ray lists");
+        return XRT_E_UNSUPPORTED;
+    }
+    const unsigned blocks = (unsigned)((P.nx * P.ny + 63) / 64);
+    auto go = [&](auto k1, auto k8) {
+        if (batch == 1)
+            hipLaunchKernelGGL(k1, dim3(blocks, 1u), dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
+        else
+            hipLaunchKernelGGL(k8, dim3(blocks, (unsigned)((batch + 7) / 8)), dim3(64 * kG2Waves), 0, s, P, sino, img,
+                               batch, wt, wt_stride);
+    };
     switch (P.mode) {
-        case MODE_PARALLEL:
-            hipLaunchKernelGGL((k_gather2d<MODE_PARALLEL, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
-                               wt_stride);
-            break;
-        case MODE_DIVERGENT:
-            hipLaunchKernelGGL((k_gather2d<MODE_DIVERGENT, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
-                               wt_stride);
-            break;
-        case MODE_ARC:
-            hipLaunchKernelGGL((k_gather2d<MODE_ARC, BB>), grid, dim3(kBlock), 0, s, P, sino, img, batch, wt,
-                               wt_stride);
-            break;
-        default:
-            set_error("no gather adjoint for ray lists");
-            return XRT_E_UNSUPPORTED;
+        case MODE_PARALLEL: go(k_gather2d<MODE_PARALLEL, 1>, k_gather2d<MODE_PARALLEL, 8>); break;
+        case MODE_DIVERGENT: go(k_gather2d<MODE_DIVERGENT, 1>, k_gather2d<MODE_DIVERGENT, 8>); break;
+        default: go(k_gather2d<MODE_ARC, 1>, k_gather2d<MODE_ARC, 8>); break;
     }
     return hip_fail(hipGetLastError(), "2D gather launch");
 }
@@ -593,9 +641,9 @@ xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* 
 xrt_status launch_adjoint_gather2d_il(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s)
 {
     const DevPlan& P = p->dp;
-    const dim3 grid((unsigned)((P.nx * P.ny + kBlock - 1) / kBlock), (unsigned)((batch + 7) / 8));
+    const dim3 grid((unsigned)((P.nx * P.ny + 63) / 64), (unsigned)((batch + 7) / 8));
     const bool vec = (batch & 3) == 0 && ((uintptr_t)sino & 15) == 0;   // 16-byte aligned groups of 4
-    auto go = [&](auto kv, auto ks) { hipLaunchKernelGGL(vec ? kv : ks, grid, dim3(kBlock), 0, s, P, sino, img,
+    auto go = [&](auto kv, auto ks) { hipLaunchKernelGGL(vec ? kv : ks, grid, dim3(64 * kG2Waves), 0, s, P, sino, img,
                                                          (int32_t)batch); };
     switch (P.mode) {
         case MODE_PARALLEL: go(k_gather2d_il<MODE_PARALLEL, true>, k_gather2d_il<MODE_PARALLEL, false>); break;

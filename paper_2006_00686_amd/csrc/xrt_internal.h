@@ -49,6 +49,14 @@ struct DevPlan {
     const double* col_cs;             // MODE_ARC: [n_cols][2] (cos, sin) of the column angle
     const double* row_cs;             // MODE_ARC: [n_rows][2]
     const double* rays;               // MODE_LIST: [n_rays][6] (p, d)
+    // 2D gather: (|d|/d_x, |d|/d_y) of every (view, column) ray (MODE_DIVERGENT, MODE_ARC:
+    // [n_views][n_cols][2]) or of every view's common direction (MODE_PARALLEL:
+    // [n_views][2]); 0 marks a zero component (ray parallel to that axis's grid lines)
+    const double* ray2d;
+    // half-width in bins by which the gathers widen a candidate column range: covers the
+    // hardware FP64 reciprocal (relative error below 2^-20) at the largest |u| of the
+    // detector
+    double uslack;
     // forward launch shape (tuning; no effect on results): packet_cols = 0 enumerates
     // rays linearly, 64 / 32 / 16 gives each wavefront a packet of packet_cols detector
     // columns x (64 / packet_cols) rows of one view; xcd_remap = 1 hands each XCD a
@@ -69,6 +77,7 @@ struct xrt_plan {
     void* d_col;
     void* d_row;
     void* d_rays;
+    void* d_ray2d;      // DevPlan::ray2d (2D plans with the gather), or NULL
     int32_t kind;
     // voxel-driven cone adjoint (flat detector): per-row 1/v table and a sinogram
     // workspace [view][col][row] of one batch member, owned by the plan
@@ -81,7 +90,7 @@ struct xrt_plan {
     int32_t helical;    // the source moves along z between views
     double sz0;         // source height of the first view (of every view when !helical)
     // y-fastest copy of one image for the forward projection of views whose detector
-    // u axis runs along y (3D scans, owned by the plan), or NULL
+    // u axis runs along y (owned by the plan; 2D plans use it for one image per call), or NULL
     float* d_imgT;
     int32_t gather2d_ok;   // 2D scan whose image lies in front of every source position
     // (f, mu) pairs of one image for the attenuated forward, allocated by its first call
@@ -156,6 +165,9 @@ xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double
 xrt_status launch_hits(const xrt_plan* p, int64_t first, int64_t n, double eps,
                        const int64_t* offsets, int32_t* idx, float* len, hipStream_t s);
 xrt_status launch_fill_zero(float* dst, int64_t n, hipStream_t s);
+// Simplex basis (xrt_simplex.hip): images of S = 2 (2D) or 6 (3D) values per unit.
+xrt_status launch_forward_simplex(const xrt_plan* p, const float* img, float* sino, int batch, hipStream_t s);
+xrt_status launch_adjoint_simplex(const xrt_plan* p, const float* sino, float* img, int batch, hipStream_t s);
 // Voxel-driven gather adjoint for flat-detector cone beams (xrt_gather.hip).
 xrt_status launch_adjoint_cone_gather(const xrt_plan* p, const float* sino, float* img, int batch,
                                       hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);

@@ -297,7 +297,7 @@ xrt_status upload(const std::vector<T>& h, void** d)
 void free_plan(xrt_plan* p)
 {
     if (!p) return;
-    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT,
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_ray2d, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT,
                     (void*)p->d_att})
         if (q) (void)hipFree(q);
     delete p;
@@ -498,9 +498,46 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
             }
         }
     }
+    // candidate column ranges of the gathers: |u| / du up to the detector's edge times the
+    // reciprocal's relative error bound, plus the exact ranges' own slack
+    D.uslack = 1e-7 + std::ldexp(std::fmax(std::fabs(D.ubase), std::fabs(D.ubase + (D.n_cols - 1) * D.du)) / D.du + 1.0,
+                                 -20);
+    D.ray2d = nullptr;
+    p->d_ray2d = nullptr;
+    if (p->gather2d_ok) {
+        // per (view, column) for rays that fan out, per view for parallel beams:
+        // |d| / d_x and |d| / d_y of the ray direction d (as the forward builds it), so that
+        // the gather's ray parameters are physical lengths
+        const bool per_col = D.mode != MODE_PARALLEL;
+        const int64_t nc = per_col ? D.n_cols : 1;
+        std::vector<double> tab((size_t)(D.n_views * nc * 2));
+        for (int32_t v = 0; v < D.n_views; ++v) {
+            const ViewGeom& V = T.views[(size_t)v];
+            for (int64_t c = 0; c < nc; ++c) {
+                double dx = V.E[0], dy = V.E[1];
+                if (D.mode == MODE_DIVERGENT) {
+                    const double u = (double)c * D.du + D.ubase;
+                    dx = V.E[0] + u * V.B[0];
+                    dy = V.E[1] + u * V.B[1];
+                } else if (D.mode == MODE_ARC) {
+                    const double ca = T.col[(size_t)(2 * c)], sa = T.col[(size_t)(2 * c + 1)];
+                    dx = ca * V.E[0] + sa * V.B[0];
+                    dy = ca * V.E[1] + sa * V.B[1];
+                }
+                const double n = std::sqrt(dx * dx + dy * dy);
+                tab[(size_t)((v * nc + c) * 2)] = dx != 0.0 ? n / dx : 0.0;
+                tab[(size_t)((v * nc + c) * 2 + 1)] = dy != 0.0 ? n / dy : 0.0;
+            }
+        }
+        if ((st = upload(tab, &p->d_ray2d)) != XRT_OK) {
+            free_plan(p);
+            return st;
+        }
+        D.ray2d = (const double*)p->d_ray2d;
+    }
     bool any_y = false;   // a view whose u axis runs closer to y than to x
     for (const ViewGeom& V : T.views) any_y = any_y || std::fabs(V.B[1]) > std::fabs(V.B[0]);
-    if (D.dim == 3 && D.mode != MODE_LIST && any_y) {
+    if (D.mode != MODE_LIST && any_y) {
         void* ws = nullptr;
         if (hipMalloc(&ws, (size_t)D.n_units * sizeof(float)) != hipSuccess) {
             (void)hipGetLastError();
@@ -638,6 +675,22 @@ xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_
                        void* stream)
 {
     return adjoint_impl(plan, d_sino, d_img, batch, mode, stream, nullptr, 0);
+}
+
+xrt_status xrt_forward_simplex(xrt_plan* plan, const float* d_img, float* d_sino, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_forward_simplex(plan, d_img, d_sino, batch, (hipStream_t)stream);
+}
+
+xrt_status xrt_adjoint_simplex(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch, void* stream)
+{
+    if (!plan || !d_img || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
+    if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
+    DeviceGuard guard(plan->device);
+    return launch_adjoint_simplex(plan, d_sino, d_img, batch, (hipStream_t)stream);
 }
 
 xrt_status xrt_forward_weighted(xrt_plan* plan, const float* d_img, const float* d_w, int32_t w_per_image,

@@ -776,7 +776,10 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
         return P.nest_z ? dispatch<FwdNestK>(P, g, s, im, imT, sn, nb, w, ws)
                         : dispatch<FwdK>(P, g, s, im, imT, sn, nb, w, ws);
     };
-    if (p->d_imgT == nullptr)
+    // one launch over the batch without the y-fastest copy (which holds one image) where
+    // there is none, or for a batch of 2D images (small, so the copies would cost more
+    // launches than they save); the values read are the same either way
+    if (p->d_imgT == nullptr || (P.dim == 2 && batch > 1))
         return launch(dim3(grid, (unsigned)batch), img, (const float*)nullptr, sino, wt, wt_stride);
     for (int b = 0; b < batch; ++b) {
         const float* im = img + (int64_t)b * P.n_units;

@@ -90,7 +90,12 @@ def test_cgls_with_stored_matrix(X):
     assert im.converged and ip.converged
     assert abs(im.iterations - ip.iterations) <= 2, (im.iterations, ip.iterations)
     k = min(len(im.rel_residual), len(ip.rel_residual))
-    np.testing.assert_allclose(im.rel_residual[:k], ip.rel_residual[:k], rtol=2e-2)
+    # The two operators agree to FP32 rounding but sum in different orders; CGLS on this
+    # ill-conditioned system amplifies such differences iteration by iteration (loss of
+    # conjugacy), so the trajectories agree closely at first and drift by a few percent
+    # after tens of iterations.
+    np.testing.assert_allclose(im.rel_residual[:8], ip.rel_residual[:8], rtol=1e-4)
+    np.testing.assert_allclose(im.rel_residual[:k], ip.rel_residual[:k], rtol=5e-2)
 
 
 def test_spmv_rejects_oversized_input(X):
