@@ -400,10 +400,10 @@ void ora_adjoint_att(const ora_grid* g, long nrays, const double* p, const doubl
  * s of unit I is the set of points whose local coordinates l_a = xi_a - floor(xi_a),
  * sorted from largest to smallest, come in the s-th order of the axes in lexicographic
  * order: 2D (x,y) = 0, (y,x) = 1; 3D (x,y,z) = 0, (x,z,y) = 1, (y,x,z) = 2,
- * (y,z,x) = 3, (z,x,y) = 4, (z,y,x) = 5.  Equal coordinates rank the later axis first,
- * which gives a point on a diagonal plane to the simplex with the bigger index (the
- * resolution of Sec. 4.1 carried to the new faces).  Simplex index = I * S + s, S = 2 (2D)
- * or 6 (3D).
+ * (y,z,x) = 3, (z,x,y) = 4, (z,y,x) = 5.  Equal coordinates (within SIMPLEX_TIE) rank the
+ * later axis first, which gives a point on a diagonal plane to the simplex with the
+ * bigger index (the resolution of Sec. 4.1 carried to the new faces).  Simplex index =
+ * I * S + s, S = 2 (2D) or 6 (3D).
  *
  * Method: the chord partition again, with the crossings of the diagonal plane families
  * xi_a - xi_b = integer added to those of the grid planes; each piece goes to the
@@ -426,16 +426,27 @@ static void index_line(const ogrid* o, const double* pu, const double* wu, doubl
     }
 }
 
+/* Local coordinates closer than this (index units) count as equal: a ray placed in a
+ * diagonal face in exact arithmetic has coordinates that differ by rounding only (the
+ * faces' counterpart of snapping tiny direction components to zero). */
+#define SIMPLEX_TIE 1e-9
+
+/* axis a ranks before axis b: larger coordinate, or equal and a the later axis */
+static int ranks_before(const double* l, int a, int b)
+{
+    if (fabs(l[a] - l[b]) <= SIMPLEX_TIE) return a > b;
+    return l[a] > l[b];
+}
+
 /* rank of the permutation that sorts the local coordinates (largest first, ties: the
  * later axis first), lexicographic over permutations */
 static int simplex_of(int dim, const double* l)
 {
-    if (dim == 2) return (l[1] >= l[0]) ? 1 : 0;
+    if (dim == 2) return ranks_before(l, 1, 0) ? 1 : 0;
     int ord[3] = {0, 1, 2};
-    /* insertion sort by "ranks before": value larger, or equal and axis later */
     for (int i = 1; i < 3; ++i) {
         int k = ord[i], j = i - 1;
-        while (j >= 0 && (l[k] > l[ord[j]] || (l[k] == l[ord[j]] && k > ord[j]))) {
+        while (j >= 0 && ranks_before(l, k, ord[j])) {
             ord[j + 1] = ord[j];
             --j;
         }

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxrt.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["xrt_plan.cpp", "xrt_project.hip", "xrt_gather.hip", "xrt_vec.hip", "xrt_conv.hip", "xrt_batch.cpp", "xrt_csr.hip"]
+SOURCES = ["xrt_plan.cpp", "xrt_project.hip", "xrt_gather.hip", "xrt_vec.hip", "xrt_conv.hip", "xrt_batch.cpp", "xrt_csr.hip",
+           "xrt_simplex.hip"]
 
 # Packed FP32 instructions are switched off for all device code; float atomics map to
 # the hardware instructions; no NaN is ever formed in the kernels (infinities are), so

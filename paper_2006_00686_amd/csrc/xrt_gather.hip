@@ -367,9 +367,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // wt: per-ray weights applied to the sinogram values (the PET form), or none.
 constexpr int kG2Waves = 4;
 
-// C_up - C_low of the ray with origin offsets a0 = xa - o_x, a1 = xb - o_x, b0 = ya - o_y,
-// b1 = yb - o_y and J (0: the ray runs along that axis's grid lines, where the pixel
-// owns x in [xa, xb) and y in (ya, yb])
+// C_up - C_low of a ray from a source (origin offsets a0 = xa - S_x, a1 = xb - S_x,
+// b0 = ya - S_y, b1 = yb - S_y, every unit at positive ray parameter) with J from the
+// plan's table.  A ray parallel to x grid lines has J_x = +1e300: its x interval is then
+// (-inf, +inf) for a0 < 0 < a1, [0, inf) for a0 = 0 and (-inf, 0] for a1 = 0 -- with the
+// unit's positive parameters, exactly the membership x in [xa, xb); J_y = -1e300 gives
+// y in (ya, yb] the same way.  No branch, no division.
+__device__ __forceinline__ double clip2d_src(double a0, double a1, double b0, double b1, double jx, double jy)
+{
+    const double t0 = a0 * jx, t1 = a1 * jx, u0 = b0 * jy, u1 = b1 * jy;
+    return fmin(fmax(t0, t1), fmax(u0, u1)) - fmax(fmin(t0, t1), fmin(u0, u1));
+}
+
+// C_up - C_low of a parallel-beam ray with origin offsets a0 = xa - o_x, a1 = xb - o_x,
+// b0 = ya - o_y, b1 = yb - o_y and J (0: the ray runs along that axis's grid lines, where
+// the pixel owns x in [xa, xb) and y in (ya, yb]; J is the view's, so such a branch is
+// taken by the whole wavefront)
 __device__ __forceinline__ double clip2d(double a0, double a1, double b0, double b1, double jx, double jy)
 {
     double lo = -kInf, hi = kInf;
@@ -390,7 +403,48 @@ __device__ __forceinline__ double clip2d(double a0, double a1, double b0, double
     return hi - lo;
 }
 
-template <int MODE, int BB>
+// Detector bins [cb, ce] whose rays can cross the pixel with corner offsets a0, a1 (x)
+// and c0y, c1y (y) from the view's origin.  Hits and lengths come from the exact clip; a
+// range only has to contain every bin that hits, and its slack covers the rounding of the
+// hardware reciprocal.  Rays from a flat-detector source (when the plan allows): the
+// centre's coordinate u_c = sdd^2 (B . p) / (E . p) and the half-width of the shadow of
+// the pixel's circumscribed disc (see DevPlan::g2_r); otherwise the four corners.
+template <int MODE>
+__device__ __forceinline__ void candidate_bins(const DevPlan& P, double a0, double a1, double c0y, double c1y,
+                                               double Bx, double By, double Ex, double Ey, double idu, int32_t& cb,
+                                               int32_t& ce)
+{
+    double umin = kInf, umax = -kInf;
+    if (MODE == MODE_DIVERGENT && P.g2_r > 0.0) {
+        const double px = 0.5 * (a0 + a1), py = 0.5 * (c0y + c1y);
+        const double e2 = Ex * Ex + Ey * Ey;                     // |E|^2 = sdd^2
+        const double r = rcp_fast(fma(px, Ex, py * Ey));
+        const double uc = e2 * fma(px, Bx, py * By) * r;
+        const double hw = (e2 + fmax(P.g2_umax2, uc * uc)) * P.g2_r * r * P.du;
+        umin = uc - hw;
+        umax = uc + hw;
+    } else {
+#pragma unroll
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const double px = (cnr & 1) ? a1 : a0, py = (cnr & 2) ? c1y : c0y;
+            double u;
+            if constexpr (MODE == MODE_PARALLEL) {
+                u = fma(px, Bx, py * By);                        // p = u B (+ t E)
+            } else if constexpr (MODE == MODE_DIVERGENT) {
+                const double e2 = Ex * Ex + Ey * Ey;
+                u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
+            } else {
+                u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));   // equiangular gamma
+            }
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+    }
+    cb = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
+    ce = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
+}
+
+template <int MODE, int BB, bool WT>
 __global__ __launch_bounds__(64 * kG2Waves) void k_gather2d(DevPlan P, const float* __restrict__ sino,
                                                              float* __restrict__ img, int32_t batch,
                                                              const float* __restrict__ wt, int64_t wt_stride)
@@ -408,56 +462,41 @@ __global__ __launch_bounds__(64 * kG2Waves) void k_gather2d(DevPlan P, const flo
     double acc[BB];
 #pragma unroll
     for (int q = 0; q < BB; ++q) acc[q] = 0.0;
+    auto value = [&](int q, int64_t r) {
+        double g = (double)sino[(int64_t)(b0 + q) * P.n_rays + r];
+        if constexpr (WT) g *= (double)wt[(int64_t)(b0 + q) * wt_stride + r];
+        return g;
+    };
     for (int32_t v = wv; v < P.n_views && live; v += kG2Waves) {
         const ViewGeom& V = P.views[v];
         const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
         // corner offsets from the view's origin (the source for rays that fan out)
         const double a0 = xa - Ax, a1 = xb - Ax, c0y = ya - Ay, c1y = yb - Ay;
-        // detector coordinate of the four corners: the candidate bins (hits and lengths
-        // come from the exact clip; the range's slack covers the reciprocal's rounding)
-        double umin = kInf, umax = -kInf;
-#pragma unroll
-        for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = (cnr & 1) ? a1 : a0, py = (cnr & 2) ? c1y : c0y;
-            double u;
-            if constexpr (MODE == MODE_PARALLEL) {
-                u = fma(px, Bx, py * By);                        // p = u B (+ t E)
-            } else if constexpr (MODE == MODE_DIVERGENT) {
-                const double e2 = Ex * Ex + Ey * Ey;             // |E|^2 = sdd^2
-                u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
-            } else {
-                u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));   // equiangular gamma
-            }
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-        }
-        const int32_t cb = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
-        const int32_t ce = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
-        double jx = 0.0, jy = 0.0;
+        int32_t cb, ce;
+        candidate_bins<MODE>(P, a0, a1, c0y, c1y, Bx, By, Ex, Ey, idu, cb, ce);
         if constexpr (MODE == MODE_PARALLEL) {
-            jx = P.ray2d[2 * v];
-            jy = P.ray2d[2 * v + 1];
-        }
-        for (int32_t c = cb; c <= ce; ++c) {
-            double len;
-            if constexpr (MODE == MODE_PARALLEL) {
+            const double jx = P.ray2d[2 * v], jy = P.ray2d[2 * v + 1];
+            for (int32_t c = cb; c <= ce; ++c) {
                 // origin A + u B moves with the bin; the direction is the view's
                 const double u = fma((double)c, P.du, P.ubase);
                 const double ox = u * Bx, oy = u * By;
-                len = clip2d(a0 - ox, a1 - ox, c0y - oy, c1y - oy, jx, jy);
-            } else {
-                const double2 J = *reinterpret_cast<const double2*>(P.ray2d + 2 * ((int64_t)v * P.n_cols + c));
-                len = clip2d(a0, a1, c0y, c1y, J.x, J.y);
-            }
-            if (!(len > 0.0)) continue;
-            const int64_t r = (int64_t)v * P.n_cols + c;
+                const double len = clip2d(a0 - ox, a1 - ox, c0y - oy, c1y - oy, jx, jy);
+                if (!(len > 0.0)) continue;
+                const int64_t r = (int64_t)v * P.n_cols + c;
 #pragma unroll
-            for (int q = 0; q < BB; ++q)
-                if (BB == 1 || b0 + q < batch) {
-                    double g = (double)sino[(int64_t)(b0 + q) * P.n_rays + r];
-                    if (wt != nullptr) g *= (double)wt[(int64_t)(b0 + q) * wt_stride + r];
-                    acc[q] = fma(g, len, acc[q]);
-                }
+                for (int q = 0; q < BB; ++q)
+                    if (BB == 1 || b0 + q < batch) acc[q] = fma(value(q, r), len, acc[q]);
+            }
+        } else {
+            for (int32_t c = cb; c <= ce; ++c) {
+                const int64_t r = (int64_t)v * P.n_cols + c;
+                const double2 J = *reinterpret_cast<const double2*>(P.ray2d + 2 * r);
+                const double len = clip2d_src(a0, a1, c0y, c1y, J.x, J.y);
+                if (!(len > 0.0)) continue;
+#pragma unroll
+                for (int q = 0; q < BB; ++q)
+                    if (BB == 1 || b0 + q < batch) acc[q] = fma(value(q, r), len, acc[q]);
+            }
         }
     }
     if (wv > 0) {
@@ -504,24 +543,8 @@ __global__ __launch_bounds__(64 * kG2Waves) void k_gather2d_il(DevPlan P, const 
         const ViewGeom& V = P.views[v];
         const double Ax = V.A[0], Ay = V.A[1], Bx = V.B[0], By = V.B[1], Ex = V.E[0], Ey = V.E[1];
         const double a0 = xa - Ax, a1 = xb - Ax, c0y = ya - Ay, c1y = yb - Ay;
-        double umin = kInf, umax = -kInf;
-#pragma unroll
-        for (int cnr = 0; cnr < 4; ++cnr) {
-            const double px = (cnr & 1) ? a1 : a0, py = (cnr & 2) ? c1y : c0y;
-            double u;
-            if constexpr (MODE == MODE_PARALLEL) {
-                u = fma(px, Bx, py * By);
-            } else if constexpr (MODE == MODE_DIVERGENT) {
-                const double e2 = Ex * Ex + Ey * Ey;   // as k_gather2d
-                u = e2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
-            } else {
-                u = atan2(fma(px, Bx, py * By), fma(px, Ex, py * Ey));
-            }
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-        }
-        const int32_t cb = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
-        const int32_t ce = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
+        int32_t cb, ce;
+        candidate_bins<MODE>(P, a0, a1, c0y, c1y, Bx, By, Ex, Ey, idu, cb, ce);
         double jx = 0.0, jy = 0.0;
         if constexpr (MODE == MODE_PARALLEL) {
             jx = P.ray2d[2 * v];
@@ -535,7 +558,7 @@ __global__ __launch_bounds__(64 * kG2Waves) void k_gather2d_il(DevPlan P, const 
                 len = clip2d(a0 - ox, a1 - ox, c0y - oy, c1y - oy, jx, jy);
             } else {
                 const double2 J = *reinterpret_cast<const double2*>(P.ray2d + 2 * ((int64_t)v * P.n_cols + c));
-                len = clip2d(a0, a1, c0y, c1y, J.x, J.y);
+                len = clip2d_src(a0, a1, c0y, c1y, J.x, J.y);
             }
             if (!(len > 0.0)) continue;
             const int64_t at = (int64_t)(v * P.n_cols + c) * batch + b0;
@@ -623,17 +646,29 @@ xrt_status launch_adjoint_gather2d(const xrt_plan* p, const float* sino, float* 
         return XRT_E_UNSUPPORTED;
     }
     const unsigned blocks = (unsigned)((P.nx * P.ny + 63) / 64);
-    auto go = [&](auto k1, auto k8) {
-        if (batch == 1)
-            hipLaunchKernelGGL(k1, dim3(blocks, 1u), dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
-        else
-            hipLaunchKernelGGL(k8, dim3(blocks, (unsigned)((batch + 7) / 8)), dim3(64 * kG2Waves), 0, s, P, sino, img,
-                               batch, wt, wt_stride);
+    auto go = [&](auto k1, auto k8, auto k1w, auto k8w) {
+        const dim3 g1(blocks, 1u), g8(blocks, (unsigned)((batch + 7) / 8));
+        if (wt == nullptr) {
+            if (batch == 1) hipLaunchKernelGGL(k1, g1, dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
+            else hipLaunchKernelGGL(k8, g8, dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
+        } else {
+            if (batch == 1) hipLaunchKernelGGL(k1w, g1, dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
+            else hipLaunchKernelGGL(k8w, g8, dim3(64 * kG2Waves), 0, s, P, sino, img, batch, wt, wt_stride);
+        }
     };
     switch (P.mode) {
-        case MODE_PARALLEL: go(k_gather2d<MODE_PARALLEL, 1>, k_gather2d<MODE_PARALLEL, 8>); break;
-        case MODE_DIVERGENT: go(k_gather2d<MODE_DIVERGENT, 1>, k_gather2d<MODE_DIVERGENT, 8>); break;
-        default: go(k_gather2d<MODE_ARC, 1>, k_gather2d<MODE_ARC, 8>); break;
+        case MODE_PARALLEL:
+            go(k_gather2d<MODE_PARALLEL, 1, false>, k_gather2d<MODE_PARALLEL, 8, false>,
+               k_gather2d<MODE_PARALLEL, 1, true>, k_gather2d<MODE_PARALLEL, 8, true>);
+            break;
+        case MODE_DIVERGENT:
+            go(k_gather2d<MODE_DIVERGENT, 1, false>, k_gather2d<MODE_DIVERGENT, 8, false>,
+               k_gather2d<MODE_DIVERGENT, 1, true>, k_gather2d<MODE_DIVERGENT, 8, true>);
+            break;
+        default:
+            go(k_gather2d<MODE_ARC, 1, false>, k_gather2d<MODE_ARC, 8, false>, k_gather2d<MODE_ARC, 1, true>,
+               k_gather2d<MODE_ARC, 8, true>);
+            break;
     }
     return hip_fail(hipGetLastError(), "2D gather launch");
 }

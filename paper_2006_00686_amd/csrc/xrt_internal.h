@@ -51,12 +51,19 @@ struct DevPlan {
     const double* rays;               // MODE_LIST: [n_rays][6] (p, d)
     // 2D gather: (|d|/d_x, |d|/d_y) of every (view, column) ray (MODE_DIVERGENT, MODE_ARC:
     // [n_views][n_cols][2]) or of every view's common direction (MODE_PARALLEL:
-    // [n_views][2]); 0 marks a zero component (ray parallel to that axis's grid lines)
+    // [n_views][2]).  A zero component (ray parallel to that axis's grid lines) is 0 for
+    // parallel beams, and +1e300 (x) / -1e300 (y) for rays from a source, where it makes
+    // the clip of a unit in front of the source the half-open membership test
     const double* ray2d;
     // half-width in bins by which the gathers widen a candidate column range: covers the
     // hardware FP64 reciprocal (relative error below 2^-20) at the largest |u| of the
     // detector
     double uslack;
+    // 2D gather, rays from a flat-detector source: candidate bins from the pixel centre's
+    // detector coordinate u_c and the half-width (sdd^2 + max(g2_umax2, u_c^2)) g2_r / D of
+    // the shadow of the pixel's circumscribed disc (D = E . (centre - source)); g2_r = 0:
+    // use the four corners instead
+    double g2_umax2, g2_r;
     // forward launch shape (tuning; no effect on results): packet_cols = 0 enumerates
     // rays linearly, 64 / 32 / 16 gives each wavefront a packet of packet_cols detector
     // columns x (64 / packet_cols) rows of one view; xcd_remap = 1 hands each XCD a

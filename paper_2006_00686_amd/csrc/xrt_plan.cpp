@@ -504,6 +504,33 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
                                  -20);
     D.ray2d = nullptr;
     p->d_ray2d = nullptr;
+    D.g2_umax2 = 0.0;
+    D.g2_r = 0.0;
+    if (p->gather2d_ok && D.mode == MODE_DIVERGENT) {
+        // A pixel lies in the disc of radius rho (half its diagonal) around its centre; the
+        // rays through the disc deviate from the centre's ray by at most
+        // alpha = asin(rho / |centre - source|) <= A rho / depth (A = asin(x) / x at the
+        // largest x = rho / depth of the image box, depth = distance along E); on the flat
+        // detector u = sdd tan(theta) moves by at most sdd sec^2(theta) per radian, with
+        // tan(theta) <= max(|u| on the detector (one bin beyond its edge), |u_c|) / sdd.
+        const double rho = 0.5 * std::sqrt(D.pdx * D.pdx + D.pdy * D.pdy);
+        double dmin = INFINITY;
+        for (const ViewGeom& V : T.views) {
+            const double en = std::sqrt(V.E[0] * V.E[0] + V.E[1] * V.E[1]);
+            for (int cnr = 0; cnr < 4; ++cnr) {
+                const double P[2] = {D.px0 + ((cnr & 1) ? D.nx * D.pdx : 0.0), D.py0 - ((cnr & 2) ? D.ny * D.pdy : 0.0)};
+                dmin = std::fmin(dmin, ((P[0] - V.A[0]) * V.E[0] + (P[1] - V.A[1]) * V.E[1]) / en);
+            }
+        }
+        const double x = rho / dmin;
+        if (x < 0.5) {
+            const double A = std::asin(x) / x * (1.0 + 1e-9);
+            const double um = std::fmax(std::fabs(D.ubase), std::fabs(D.ubase + (D.n_cols - 1) * D.du)) + D.du;
+            D.g2_umax2 = um * um;
+            // hw (bins) = (sdd^2 + m) / sdd * alpha / du with alpha <= A rho sdd / D
+            D.g2_r = A * rho / D.du;
+        }
+    }
     if (p->gather2d_ok) {
         // per (view, column) for rays that fan out, per view for parallel beams:
         // |d| / d_x and |d| / d_y of the ray direction d (as the forward builds it), so that
@@ -525,8 +552,12 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
                     dy = ca * V.E[1] + sa * V.B[1];
                 }
                 const double n = std::sqrt(dx * dx + dy * dy);
-                tab[(size_t)((v * nc + c) * 2)] = dx != 0.0 ? n / dx : 0.0;
-                tab[(size_t)((v * nc + c) * 2 + 1)] = dy != 0.0 ? n / dy : 0.0;
+                // a zero component: 0 for parallel beams; for rays from a source, +1e300 (x)
+                // and -1e300 (y), which turn the clip of a unit in front of the source into
+                // the half-open membership test (x in [xa, xb), y in (ya, yb])
+                const double zx = per_col ? 1e300 : 0.0, zy = per_col ? -1e300 : 0.0;
+                tab[(size_t)((v * nc + c) * 2)] = dx != 0.0 ? n / dx : zx;
+                tab[(size_t)((v * nc + c) * 2 + 1)] = dy != 0.0 ? n / dy : zy;
             }
         }
         if ((st = upload(tab, &p->d_ray2d)) != XRT_OK) {

@@ -87,6 +87,44 @@ struct FwdVisit {
     }
 };
 
+// FwdVisit for 2D walks, whose slabs have two candidates: the loaded values are summed
+// two slabs after their loads are issued (same order of the sum), so that up to four
+// loads of a lane are in flight.
+struct FwdVisit2 {
+    static constexpr int32_t kIndexScale = 4;
+    __amdgpu_buffer_rsrc_t rsrc;
+    double acc;
+    float p1 = 0.0f, p2 = 0.0f, r1 = 0.0f, r2 = 0.0f;     // two slabs ago, one slab ago
+    double q1 = 0.0, q2 = 0.0, s1 = 0.0, s2 = 0.0;
+    __device__ __forceinline__ float load(int32_t off)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+    }
+    __device__ __forceinline__ void consume()
+    {
+        acc = fma((double)p1, q1, acc);
+        acc = fma((double)p2, q2, acc);
+        acc = fma((double)r1, s1, acc);
+        acc = fma((double)r2, s2, acc);
+    }
+    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    {
+        const float f1 = load(I1);
+        const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
+        acc = fma((double)p1, q1, acc);
+        acc = fma((double)p2, q2, acc);
+        p1 = r1;
+        p2 = r2;
+        q1 = s1;
+        q2 = s2;
+        r1 = f1;
+        r2 = f2;
+        s1 = l1;
+        s2 = l2;
+    }
+    __device__ __forceinline__ void three(int32_t, double, int32_t, double, int32_t, double) {}
+};
+
 // FwdVisit for a batch in the lanes of a wavefront: every lane walks the same ray (the
 // walk's values are the same in all lanes) and reads its own image's value of each unit
 // from the interleaved layout [unit][image], so the batch's values of a unit are one
@@ -425,7 +463,7 @@ __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const f
             }
         }
     }
-    FwdVisit v{image_rsrc(base, (int32_t)(P.n_units * 4)), 0.0};
+    std::conditional_t<DIM == 2, FwdVisit2, FwdVisit> v{image_rsrc(base, (int32_t)(P.n_units * 4)), 0.0};
     walk<DIM, NEST>(P, R, v);
     v.consume();
     // wt: a per-ray weight (the PET form of the generalised transform), or none

@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "xrt_internal.h"
 
@@ -189,6 +190,13 @@ XRT_HD bool setup_axes(const DevPlan& P, const Ray& R, Axis* ax,
     return true;
 }
 
+// A visitor with a member start(tin) is told the ray parameter at which the chord enters
+// the image; the pieces it is then given follow each other without gaps from there.
+template <class V, class = void>
+struct wants_start : std::false_type {};
+template <class V>
+struct wants_start<V, std::void_t<decltype(&V::start)>> : std::true_type {};
+
 // Walk the chord slab by slab.  The visitor receives the candidate units of every slab
 // with their C_up - C_low in ray-parameter units: vis.two(I1, l1, I2, l2) (2D) or
 // vis.three(I1, l1, I2, l2, I3, l3) (3D), where I1 -- the unit the ray is in at slab
@@ -215,6 +223,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
     Axis ax[3];
     double tin, tout;
     if (!setup_axes<DIM>(P, R, ax, tin, tout)) return;
+    if constexpr (wants_start<Visit>::value) vis.start(tin);
     constexpr int32_t SC = Visit::kIndexScale;
 
     int32_t I = 0;

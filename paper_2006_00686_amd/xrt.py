@@ -91,6 +91,8 @@ def _lib():
         lib.xrt_batch_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
         lib.xrt_forward_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
         lib.xrt_adjoint_attenuated.argtypes = [vp, vp, vp, i32, vp, i32, vp]
+        lib.xrt_forward_simplex.argtypes = [vp, vp, vp, i32, vp]
+        lib.xrt_adjoint_simplex.argtypes = [vp, vp, vp, i32, vp]
         lib.xrt_forward_weighted.argtypes = [vp, vp, vp, i32, vp, i32, vp]
         lib.xrt_adjoint_weighted.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp]
         lib.xrt_ray_transmission.argtypes = [vp, vp, vp, i32, vp]
@@ -185,6 +187,8 @@ class Plan:
             else:
                 self.sino_shape = (s.n_views, s.n_rows, s.n_cols)
         self.image_shape = (int(grid["ny"]), int(grid["nx"])) if nz == 0 else (nz, int(grid["ny"]), int(grid["nx"]))
+        # images on the simplex basis: 2 triangles per pixel, 6 tetrahedra per voxel
+        self.simplex_image_shape = tuple(self.image_shape) + (2 if nz == 0 else 6,)
         h = ctypes.c_void_p()
         _check(lib.xrt_plan_create(ctypes.byref(g), ctypes.byref(s), self.device, ctypes.byref(h)),
                "xrt_plan_create")
@@ -254,6 +258,27 @@ class Plan:
         self._dev_check(out)
         _check(_lib().xrt_adjoint(self._h, _ptr(sino), _ptr(out), b, ADJ[mode], _stream(self.device)),
                "xrt_adjoint")
+        return out
+
+    def forward_simplex(self, img: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Transform of an image on the simplex basis ([..., *simplex_image_shape])."""
+        self._dev_check(img)
+        lead, b = self._batch(img, self.simplex_image_shape)
+        if out is None:
+            out = torch.empty(lead + tuple(self.sino_shape), dtype=torch.float32, device=img.device)
+        self._dev_check(out)
+        _check(_lib().xrt_forward_simplex(self._h, _ptr(img), _ptr(out), b, _stream(self.device)),
+               "xrt_forward_simplex")
+        return out
+
+    def adjoint_simplex(self, sino: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._dev_check(sino)
+        lead, b = self._batch(sino, self.sino_shape)
+        if out is None:
+            out = torch.empty(lead + tuple(self.simplex_image_shape), dtype=torch.float32, device=sino.device)
+        self._dev_check(out)
+        _check(_lib().xrt_adjoint_simplex(self._h, _ptr(sino), _ptr(out), b, _stream(self.device)),
+               "xrt_adjoint_simplex")
         return out
 
     def _mu(self, mu: torch.Tensor, b: int) -> int:

@@ -8,12 +8,16 @@
 //            has_z has_phi2 n_rays eps" / then the view angles, view_z, phi2 and ray
 //            parameters as whitespace-separated numbers.
 // hits.bin: per ray int32 count, then count x (int32 index, float64 length).
+// With a third argument "simplex" the hit lists are those of the simplex basis
+// (xrt_simplex.h: each hit unit's piece cut into its simplex pieces, index I * S + s),
+// and every simplex index is checked to lie inside the simplex image.
 #include <cstdio>
 #include <cmath>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
-#include "../../paper_2006_00686_amd/csrc/xrt_walk.h"
+#include "../../paper_2006_00686_amd/csrc/xrt_simplex.h"
 
 using namespace xrt;
 
@@ -55,9 +59,48 @@ struct CheckVisit {
     }
 };
 
+template <int DIM>
+struct SimplexCheck : SimplexWalker<DIM, SimplexCheck<DIM>> {
+    int64_t n_simplices;
+    double scale;
+    std::vector<int32_t> idx;
+    std::vector<double> len;
+    long bad = 0;
+    void simplex(int64_t T, double l)
+    {
+        if (T < 0 || T >= n_simplices || !(l > 0.0)) ++bad;
+        idx.push_back((int32_t)T);
+        len.push_back(l * scale);
+    }
+};
+
 template <int DIM, int MODE>
-long run(const DevPlan& P, double eps, FILE* out)
+long run_simplex(const DevPlan& P, FILE* out)
 {
+    long bad = 0;
+    for (int32_t r = 0; r < (int32_t)P.n_rays; ++r) {
+        Ray R;
+        make_ray<DIM, MODE>(P, r, R);
+        SimplexCheck<DIM> v;
+        simplex_walker_init(v, P, R);
+        v.n_simplices = P.n_units * kSimplices<DIM>;
+        v.scale = R.scale;
+        walk<DIM>(P, R, v);
+        bad += v.bad;
+        int32_t n = (int32_t)v.idx.size();
+        fwrite(&n, 4, 1, out);
+        for (int32_t k = 0; k < n; ++k) {
+            fwrite(&v.idx[k], 4, 1, out);
+            fwrite(&v.len[k], 8, 1, out);
+        }
+    }
+    return bad;
+}
+
+template <int DIM, int MODE>
+long run(const DevPlan& P, double eps, FILE* out, bool simplex)
+{
+    if (simplex) return run_simplex<DIM, MODE>(P, out);
     long bad = 0;
     for (int32_t r = 0; r < (int32_t)P.n_rays; ++r) {
         Ray R;
@@ -83,13 +126,13 @@ long run(const DevPlan& P, double eps, FILE* out)
 }
 
 template <int DIM>
-long run_dim(const DevPlan& P, double eps, FILE* out)
+long run_dim(const DevPlan& P, double eps, FILE* out, bool simplex)
 {
     switch (P.mode) {
-        case MODE_PARALLEL: return run<DIM, MODE_PARALLEL>(P, eps, out);
-        case MODE_DIVERGENT: return run<DIM, MODE_DIVERGENT>(P, eps, out);
-        case MODE_ARC: return run<DIM, MODE_ARC>(P, eps, out);
-        default: return run<DIM, MODE_LIST>(P, eps, out);
+        case MODE_PARALLEL: return run<DIM, MODE_PARALLEL>(P, eps, out, simplex);
+        case MODE_DIVERGENT: return run<DIM, MODE_DIVERGENT>(P, eps, out, simplex);
+        case MODE_ARC: return run<DIM, MODE_ARC>(P, eps, out, simplex);
+        default: return run<DIM, MODE_LIST>(P, eps, out, simplex);
     }
 }
 
@@ -105,7 +148,11 @@ std::vector<double> read_n(FILE* f, long n)
 
 int main(int argc, char** argv)
 {
-    if (argc != 3) { fprintf(stderr, "usage: walk_check scan.txt hits.bin\n"); return 2; }
+    if (argc != 3 && !(argc == 4 && std::string(argv[3]) == "simplex")) {
+        fprintf(stderr, "usage: walk_check scan.txt hits.bin [simplex]\n");
+        return 2;
+    }
+    const bool simplex = argc == 4;
     FILE* f = fopen(argv[1], "r");
     if (!f) return 2;
     xrt_grid g{};
@@ -139,7 +186,7 @@ int main(int argc, char** argv)
     T.dp.rays = T.rays.data();
     FILE* out = fopen(argv[2], "wb");
     if (!out) return 2;
-    long bad = T.dp.dim == 2 ? run_dim<2>(T.dp, eps, out) : run_dim<3>(T.dp, eps, out);
+    long bad = T.dp.dim == 2 ? run_dim<2>(T.dp, eps, out, simplex) : run_dim<3>(T.dp, eps, out, simplex);
     fclose(out);
     if (bad) { fprintf(stderr, "%ld out-of-range image indices or contract violations\n", bad); return 3; }
     return 0;

@@ -35,7 +35,7 @@ def walker(tmp_path_factory):
     return exe
 
 
-def run_walk(exe, tmpdir, grid, scan, eps=0.0):
+def run_walk(exe, tmpdir, grid, scan, eps=0.0, simplex=False):
     kind = scan["kind"]
     vals = [KIND[kind], grid["nx"], grid["ny"], grid.get("nz", 0), grid.get("dx", 1.0), grid.get("dy", 1.0),
             grid.get("dz", 1.0), grid.get("cx", 0.0), grid.get("cy", 0.0), grid.get("cz", 0.0)]
@@ -58,7 +58,7 @@ def run_walk(exe, tmpdir, grid, scan, eps=0.0):
         f.write(" ".join(repr(float(v)) if isinstance(v, float) else str(v) for v in head2) + "\n")
         for b in body:
             f.write(" ".join(repr(float(x)) for x in b) + "\n")
-    res = subprocess.run([exe, sp, hp_], capture_output=True, text=True)
+    res = subprocess.run([exe, sp, hp_] + (["simplex"] if simplex else []), capture_output=True, text=True)
     assert res.returncode == 0, res.stderr
     rows = []
     with open(hp_, "rb") as f:
@@ -143,3 +143,55 @@ def test_host_walk_par2d_128_full(walker, tmp_path):
     img = inputs.make_image(cfg)
     ref, scl = H.forward_bar(cfg["grid"], cfg["scan"], img)
     H.assert_within_bar(dense_forward(rows, img), ref, scl, rtol=1e-9, what="par2d_128 host walk")
+
+
+# ------------------------------------------------------------------ simplex basis
+
+def dense_rows(rows, n):
+    """Dense per-ray vectors from hit lists (repeated indices summed)."""
+    out = np.zeros((len(rows), n))
+    for r, (i, l) in enumerate(rows):
+        np.add.at(out[r], i, l)
+    return out
+
+
+@pytest.mark.parametrize("name,grid,scan", SCANS, ids=[s[0] for s in SCANS])
+def test_host_simplex_walk_matches_oracle(walker, tmp_path, name, grid, scan):
+    """The kernels' simplex cutting (xrt_simplex.h) run on the host over every scan kind:
+    every simplex index in range, and line integrals of a random simplex image equal to
+    the FP64 simplex oracle's."""
+    rows = run_walk(walker, str(tmp_path), grid, scan, simplex=True)
+    img = np.random.default_rng(8).uniform(size=ocore.simplex_image_shape(grid))
+    p, th = ogeom.expand(scan)
+    ref = ocore.forward_simplex_lines(grid, p, th, img)
+    scl = ocore.forward_simplex_lines(grid, p, th, np.abs(img))
+    got = np.array([float(np.dot(img.ravel()[i], l)) for i, l in rows])
+    H.assert_within_bar(got, ref, scl, rtol=1e-9, what=f"host simplex walk {name}")
+
+
+@pytest.mark.parametrize("d3", [False, True])
+def test_host_simplex_walk_random_and_aligned_rays(walker, tmp_path, d3):
+    """Per-simplex lengths against the oracle's, ray by ray, on random rays and on rays
+    along the grid and diagonal planes (the resolution of Sec. 4.1 on both kinds of
+    face)."""
+    grid = dict(nx=7, ny=6, nz=(5 if d3 else 0), dx=1.0, dy=1.0, dz=1.0)
+    rays = (inputs.random_rays3d if d3 else inputs.random_rays2d)(800, 5.0, 15 + d3)
+    al = []
+    for s in np.arange(-4, 4.5, 0.5):
+        if d3:
+            for s2 in (-2.5, -1.0, 0.0, 1.5, 2.5):
+                al += [[s, s2, 0.0, 0.0], [s, s2, PI / 2, 0.0], [s, s2, 0.0, PI / 2], [s, s2, PI / 4, 0.0],
+                       [s, s2, 3 * PI / 4, 0.0], [s, s2, 0.0, PI / 4]]
+        else:
+            al += [[s, 0.0], [s, PI / 2], [s, PI / 4], [s, 3 * PI / 4], [s, -PI / 4]]
+    rays = np.concatenate([rays, np.array(al)], axis=0)
+    kind = "raylist3d" if d3 else "raylist2d"
+    rows = run_walk(walker, str(tmp_path), grid, dict(kind=kind, rays=rays), simplex=True)
+    p, th = (ogeom.par3d_lines(*rays.T) if d3 else ogeom.par2d_lines(*rays.T))
+    n = int(np.prod(ocore.simplex_image_shape(grid)))
+    got = dense_rows(rows, n)
+    for r in range(len(rays)):
+        want = np.zeros(n)
+        oi, ol = ocore.ray_hits_simplex_line(grid, p[r], th[r], 0.0)
+        np.add.at(want, oi, ol)
+        np.testing.assert_allclose(got[r], want, atol=1e-9, err_msg=f"ray {r} {rays[r]}")
