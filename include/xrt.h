@@ -28,10 +28,12 @@
  *   them.  Host arrays referenced by xrt_scan are copied during xrt_plan_create.
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
  *   asynchronously; no call below synchronises the host except plan create/destroy and
- *   the first xrt_forward_attenuated on a plan outside stream capture (it allocates that
- *   plan's workspace).  Nothing allocates during stream capture.
+ *   the first attenuated call (xrt_forward_attenuated or xrt_adjoint_attenuated) on a
+ *   plan outside stream capture (it allocates that plan's workspace).  Nothing allocates
+ *   during stream capture.
  * Concurrency: a plan's device workspaces (the cone gather's transposed sinogram, the
- *   forward's y-fastest copy, the attenuated forward's pairs) are shared by its calls, so
+ *   y-fastest copy of an image, the attenuated transform's workspace) are shared by its
+ *   calls, so
  *   calls on one plan must be ordered: one stream, or events between streams.  Different
  *   plans are independent.
  * Errors: every call returns an xrt_status.  Arguments are validated before any work
@@ -249,11 +251,13 @@ xrt_status xrt_conv3x3_wgrad(int32_t cin, int32_t cout, int32_t batch, int32_t h
  * contributes f exp(-A) (1 - exp(-mu len)) / mu (f len where mu = 0), A the attenuation
  * between the piece and the detector.  The adjoint is the exact transpose (ray-driven,
  * atomics: summation order not fixed).  Same layouts and errors as xrt_forward.  The
- * forward's first call on a plan outside stream capture allocates a workspace of
- * 2 n_units floats that the plan keeps (XRT_E_NOMEM if that fails); it interleaves each
- * image with its map, so that a candidate takes one 8-byte load.  A call during capture
- * on a plan without it reads image and map separately and allocates nothing (same
- * results). */
+ * first attenuated call on a plan outside stream capture allocates a workspace of
+ * 2 n_units floats that the plan keeps (XRT_E_NOMEM if that fails): the forward
+ * interleaves each image with its map there, so that a candidate takes one 8-byte load;
+ * the adjoint of a 3D plan keeps a y-fastest copy of the map there for the views whose
+ * atomics it adds into the y-fastest layout.  A call during capture on a plan without it
+ * allocates nothing and takes the paths that need none (same results up to the adjoint's
+ * summation order). */
 xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const float* d_mu, int32_t mu_per_image,
                                   float* d_sino, int32_t batch, void* stream);
 xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const float* d_mu, int32_t mu_per_image,

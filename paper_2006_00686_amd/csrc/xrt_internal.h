@@ -162,8 +162,9 @@ xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const Dev
 xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, hipStream_t s);
 xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride, float* sino,
                               int batch, hipStream_t s);
+// muT: n_units floats of workspace for the map's y-fastest copy, or NULL
 xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float* mu, int64_t mu_stride, float* img,
-                              int batch, hipStream_t s);
+                              int batch, hipStream_t s, float* muT = nullptr);
 uint32_t forward_batch_blocks_per_cu();
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
                                   hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);

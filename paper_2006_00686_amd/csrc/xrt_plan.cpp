@@ -611,6 +611,32 @@ xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_
     return launch_forward(plan, d_img, d_sino, batch, (hipStream_t)stream);
 }
 
+namespace {
+
+// The attenuated transform's plan workspace of 2 n_units floats, allocated on first use
+// (never during stream capture: a captured call without it takes the path that needs
+// none and allocates nothing).  XRT_OK with plan->d_att possibly still NULL.
+xrt_status ensure_att_workspace(xrt_plan* plan, void* stream)
+{
+    if (plan->d_att != nullptr || plan->dp.n_units * 8 > (int64_t)INT32_MAX - 16) return XRT_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusActive;
+    }
+    if (cs != hipStreamCaptureStatusNone) return XRT_OK;
+    void* ws = nullptr;
+    if (hipMalloc(&ws, (size_t)plan->dp.n_units * 2 * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the %lld-float attenuated-transform workspace failed", (long long)plan->dp.n_units * 2);
+        return XRT_E_NOMEM;
+    }
+    plan->d_att = (float*)ws;
+    return XRT_OK;
+}
+
+}  // namespace
+
 xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const float* d_mu, int32_t mu_per_image,
                                   float* d_sino, int32_t batch, void* stream)
 {
@@ -618,29 +644,11 @@ xrt_status xrt_forward_attenuated(xrt_plan* plan, const float* d_img, const floa
     if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
     DeviceGuard guard(plan->device);
     const int64_t mu_stride = mu_per_image ? plan->dp.n_units : 0;
-    // (f, mu) interleaved, so that each candidate takes one 8-byte load; the pairs of
-    // one image live in a plan workspace allocated here on first use
-    // (never during stream capture: a captured call without the workspace takes the
-    // unpaired walk and allocates nothing)
-    if (plan->dp.n_units * 8 <= (int64_t)INT32_MAX - 16) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (plan->d_att == nullptr && hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) {
-            (void)hipGetLastError();
-            cs = hipStreamCaptureStatusActive;
-        }
-        if (plan->d_att == nullptr && cs == hipStreamCaptureStatusNone) {
-            void* ws = nullptr;
-            if (hipMalloc(&ws, (size_t)plan->dp.n_units * 2 * sizeof(float)) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("hipMalloc of the %lld-float attenuated-forward workspace failed",
-                          (long long)plan->dp.n_units * 2);
-                return XRT_E_NOMEM;
-            }
-            plan->d_att = (float*)ws;
-        }
-        if (plan->d_att != nullptr)
-            return launch_forward_att_pairs(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
-    }
+    // (f, mu) interleaved in the workspace, so that each candidate takes one 8-byte load
+    const xrt_status st = ensure_att_workspace(plan, stream);
+    if (st != XRT_OK) return st;
+    if (plan->d_att != nullptr)
+        return launch_forward_att_pairs(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
     return launch_forward_att(plan, d_img, d_mu, mu_stride, d_sino, batch, (hipStream_t)stream);
 }
 
@@ -650,8 +658,12 @@ xrt_status xrt_adjoint_attenuated(xrt_plan* plan, const float* d_sino, const flo
     if (!plan || !d_img || !d_mu || !d_sino) { set_error("null argument"); return XRT_E_ARG; }
     if (batch < 1 || batch > 65535) { set_error("batch must be in [1, 65535]"); return XRT_E_ARG; }
     DeviceGuard guard(plan->device);
+    // the map's y-fastest copy for the views that scatter into the y-fastest layout
+    // lives in the workspace's first half
+    const xrt_status st = ensure_att_workspace(plan, stream);
+    if (st != XRT_OK) return st;
     return launch_adjoint_att(plan, d_sino, d_mu, mu_per_image ? plan->dp.n_units : 0, d_img, batch,
-                              (hipStream_t)stream);
+                              (hipStream_t)stream, plan->d_att);
 }
 
 namespace {

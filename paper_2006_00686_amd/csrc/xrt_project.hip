@@ -440,6 +440,22 @@ __host__ __device__ inline uint64_t forward_threads(const DevPlan& P)
     return (uint64_t)P.n_views * ((P.n_cols + tw - 1) / tw) * ((P.n_rows + th - 1) / th) * 64u;
 }
 
+// A wavefront's rays step along the image with its lanes spread along the detector's u
+// axis; where u runs closer to y than to x, a scatter into the y-fastest layout keeps a
+// wavefront's atomic adds in few cache lines (the view's choice, as the forward's).
+template <int MODE>
+__device__ __forceinline__ bool view_prefers_y_fastest(const DevPlan& P, int32_t r)
+{
+    if constexpr (MODE == MODE_LIST) {
+        return false;
+    } else {
+        const uint32_t per_view = (uint32_t)P.n_rows * (uint32_t)P.n_cols;
+        const uint32_t view0 = __builtin_amdgcn_readfirstlane((uint32_t)r / per_view);
+        const ViewGeom& V = P.views[view0];
+        return fabs(V.B[1]) > fabs(V.B[0]);
+    }
+}
+
 // Whether this lane's rays would rather read the y-fastest copy: the lanes of a
 // wavefront walk neighbouring rays one slab per step, so at every step they sit where
 // their entry points sit, shifted along the ray -- spread along the entry face.  A chord
@@ -640,8 +656,11 @@ __global__ __launch_bounds__(kBlock) void k_att_pairs(const float* __restrict__ 
 }
 
 template <int DIM, int MODE>
+// imgT, muT (one image, y fastest; imgT zeroed) or NULL: views whose u axis runs along y
+// read the map from muT and add into imgT (see view_prefers_y_fastest).
 __global__ __launch_bounds__(kBlock) void k_adjoint_att(DevPlan P, const float* __restrict__ sino,
-                                                         const float* __restrict__ mu, int64_t mu_stride, float* img)
+                                                         const float* __restrict__ mu, int64_t mu_stride, float* img,
+                                                         float* imgT, const float* __restrict__ muT)
 {
     const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (r >= P.n_rays) return;
@@ -652,8 +671,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_att(DevPlan P, const float* 
     make_ray<DIM, MODE>(P, r, R);
 #pragma unroll
     for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];
-    AttAdjVisit v{img + b * P.n_units, image_rsrc(mu + b * mu_stride, (int32_t)(P.n_units * 4)), R.scale, (double)g,
-                  0.0};
+    float* out = img + b * P.n_units;
+    const float* m = mu + b * mu_stride;
+    if (imgT != nullptr && view_prefers_y_fastest<MODE>(P, r)) {
+        out = imgT;
+        m = muT;
+        R.st[0] = P.ny;
+        R.st[1] = 1;
+    }
+    AttAdjVisit v{out, image_rsrc(m, (int32_t)(P.n_units * 4)), R.scale, (double)g, 0.0};
     walk<DIM>(P, R, v);
 }
 
@@ -682,10 +708,33 @@ __global__ __launch_bounds__(kBlock) void k_transpose_xy(const float* __restrict
     }
 }
 
+// out[z][y][x] += in[z][x][y]
+__global__ __launch_bounds__(kBlock) void k_add_transposed_xy(const float* __restrict__ in, float* __restrict__ out,
+                                                               int32_t nx, int32_t ny, int32_t ytiles)
+{
+    __shared__ float tile[32][33];
+    const int32_t z = blockIdx.y / ytiles;
+    const int32_t y0 = (blockIdx.y - z * ytiles) * 32, x0 = blockIdx.x * 32;
+    const int32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t slab = (int64_t)z * nx * ny;
+    for (int32_t xx = ty; xx < 32; xx += kBlock / 32) {
+        const int32_t x = x0 + xx, y = y0 + tx;
+        if (y < ny && x < nx) tile[xx][tx] = in[slab + (int64_t)x * ny + y];
+    }
+    __syncthreads();
+    for (int32_t yy = ty; yy < 32; yy += kBlock / 32) {
+        const int32_t y = y0 + yy, x = x0 + tx;
+        if (y < ny && x < nx) out[slab + (int64_t)y * nx + x] += tile[tx][yy];
+    }
+}
+
 // wt: per-ray weights applied to the sinogram values (the PET form), or none.
+// imgT (one image, y fastest, zeroed) or NULL: views whose u axis runs along y add into
+// it, to be added back transposed.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_scatter(DevPlan P, const float* __restrict__ sino,
-                                                     float* img, const float* __restrict__ wt, int64_t wt_stride)
+                                                     float* img, const float* __restrict__ wt, int64_t wt_stride,
+                                                     float* imgT)
 {
     const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (r >= P.n_rays) return;
@@ -694,7 +743,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(DevPlan P, const float* __re
     if (g == 0.0) return;
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
-    ScatterVisit v{img + b * P.n_units, g * R.scale};
+    float* out = img + b * P.n_units;
+    if (imgT != nullptr && view_prefers_y_fastest<MODE>(P, r)) {
+        out = imgT;
+        R.st[0] = P.ny;
+        R.st[1] = 1;
+    }
+    ScatterVisit v{out, g * R.scale};
     walk<DIM>(P, R, v);
 }
 
@@ -963,13 +1018,37 @@ xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const f
     return XRT_OK;
 }
 
+xrt_status launch_add_transposed_xy(const DevPlan& P, const float* imgT, float* img, hipStream_t s)
+{
+    const int32_t ytiles = (P.ny + 31) / 32;
+    hipLaunchKernelGGL(k_add_transposed_xy, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ytiles * P.nz)),
+                       dim3(kBlock), 0, s, imgT, img, P.nx, P.ny, ytiles);
+    return hip_fail(hipGetLastError(), "transposed add launch");
+}
+
+// The scatters of 3D plans with a y-fastest workspace add the views whose u axis runs
+// along y into it (zeroed first) and add it back transposed, one image at a time; the
+// attenuated one also reads those views' map from a y-fastest copy (muT: n_units floats
+// of plan workspace, or NULL to keep one layout).
 xrt_status launch_adjoint_att(const xrt_plan* p, const float* sino, const float* mu, int64_t mu_stride, float* img,
-                              int batch, hipStream_t s)
+                              int batch, hipStream_t s, float* muT)
 {
     const DevPlan& P = p->dp;
     xrt_status st = launch_fill_zero(img, P.n_units * (int64_t)batch, s);
     if (st != XRT_OK) return st;
-    return dispatch<AdjAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, mu, mu_stride, img);
+    if (P.dim != 3 || p->d_imgT == nullptr || muT == nullptr)
+        return dispatch<AdjAttK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, mu, mu_stride, img,
+                                 (float*)nullptr, (const float*)nullptr);
+    for (int b = 0; b < batch; ++b) {
+        if ((st = launch_fill_zero(p->d_imgT, P.n_units, s)) != XRT_OK) return st;
+        if ((st = launch_transpose_xy(P, mu + (int64_t)b * mu_stride, muT, s)) != XRT_OK) return st;
+        st = dispatch<AdjAttK>(P, dim3(blocks_for(P.n_rays), 1u), s, sino + (int64_t)b * P.n_rays,
+                               mu + (int64_t)b * mu_stride, (int64_t)0, img + (int64_t)b * P.n_units, p->d_imgT,
+                               (const float*)muT);
+        if (st != XRT_OK) return st;
+        if ((st = launch_add_transposed_xy(P, p->d_imgT, img + (int64_t)b * P.n_units, s)) != XRT_OK) return st;
+    }
+    return XRT_OK;
 }
 
 xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* img, int batch,
@@ -978,7 +1057,18 @@ xrt_status launch_adjoint_scatter(const xrt_plan* p, const float* sino, float* i
     const DevPlan& P = p->dp;
     xrt_status st = launch_fill_zero(img, P.n_units * (int64_t)batch, s);
     if (st != XRT_OK) return st;
-    return dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, img, wt, wt_stride);
+    if (P.dim != 3 || p->d_imgT == nullptr)
+        return dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), (unsigned)batch), s, sino, img, wt, wt_stride,
+                               (float*)nullptr);
+    for (int b = 0; b < batch; ++b) {
+        if ((st = launch_fill_zero(p->d_imgT, P.n_units, s)) != XRT_OK) return st;
+        st = dispatch<ScatK>(P, dim3(blocks_for(P.n_rays), 1u), s, sino + (int64_t)b * P.n_rays,
+                             img + (int64_t)b * P.n_units, wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr,
+                             (int64_t)0, p->d_imgT);
+        if (st != XRT_OK) return st;
+        if ((st = launch_add_transposed_xy(P, p->d_imgT, img + (int64_t)b * P.n_units, s)) != XRT_OK) return st;
+    }
+    return XRT_OK;
 }
 
 xrt_status launch_hit_counts(const xrt_plan* p, int64_t first, int64_t n, double eps, int32_t* counts,
