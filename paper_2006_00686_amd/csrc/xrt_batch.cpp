@@ -28,12 +28,25 @@ extern "C" {
 xrt_status xrt_plan_set_tuning(xrt_plan* plan, const xrt_tuning* t)
 {
     if (!plan || !t) { set_error("null argument"); return XRT_E_ARG; }
-    if (!(t->packet_cols == 0 || t->packet_cols == 16 || t->packet_cols == 32 || t->packet_cols == 64) ||
+    if (!(t->packet_cols == 0 || t->packet_cols == 1 || t->packet_cols == 16 || t->packet_cols == 32 ||
+          t->packet_cols == 64) ||
         (t->xcd_remap != 0 && t->xcd_remap != 1)) {
-        set_error("packet_cols must be 0, 16, 32 or 64 and xcd_remap 0 or 1");
+        set_error("packet_cols must be 0, 1, 16, 32 or 64 and xcd_remap 0 or 1");
         return XRT_E_ARG;
     }
-    plan->dp.packet_cols = plan->dp.mode == MODE_LIST ? 0 : t->packet_cols;
+    const int32_t pc = plan->dp.mode == MODE_LIST ? 0 : t->packet_cols;
+    if (pc == 1 && plan->dp.dim == 3 && plan->d_imgZ == nullptr) {
+        // column packets read a z-fastest copy of the image (plan workspace, kept)
+        DeviceGuard guard(plan->device);
+        void* ws = nullptr;
+        if (hipMalloc(&ws, (size_t)plan->dp.n_units * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of the %lld-float column-packet workspace failed", (long long)plan->dp.n_units);
+            return XRT_E_NOMEM;
+        }
+        plan->d_imgZ = (float*)ws;
+    }
+    plan->dp.packet_cols = pc;
     plan->dp.xcd_remap = t->xcd_remap;
     return XRT_OK;
 }

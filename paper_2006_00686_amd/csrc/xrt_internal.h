@@ -99,6 +99,10 @@ struct xrt_plan {
     // y-fastest copy of one image for the forward projection of views whose detector
     // u axis runs along y (owned by the plan; 2D plans use it for one image per call), or NULL
     float* d_imgT;
+    // z-fastest copy ([y][x][z]) of one image for the column-packet launch shape
+    // (packet_cols = 1: a wavefront takes 64 rows of one detector column), allocated when
+    // that shape is selected, or NULL
+    float* d_imgZ;
     int32_t gather2d_ok;   // 2D scan whose image lies in front of every source position
     // (f, mu) pairs of one image for the attenuated forward, allocated by its first call
     // (2 n_units floats), or NULL

@@ -297,7 +297,7 @@ xrt_status upload(const std::vector<T>& h, void** d)
 void free_plan(xrt_plan* p)
 {
     if (!p) return;
-    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_ray2d, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT,
+    for (void* q : {p->d_views, p->d_col, p->d_row, p->d_rays, p->d_ray2d, p->d_invwz, (void*)p->d_gT, (void*)p->d_imgT, (void*)p->d_imgZ,
                     (void*)p->d_att})
         if (q) (void)hipFree(q);
     delete p;

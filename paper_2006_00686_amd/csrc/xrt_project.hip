@@ -493,13 +493,24 @@ __device__ __forceinline__ bool prefers_y_fastest(const DevPlan& P, const Ray& R
 // runs closer to y than to x: choosing per wavefront there made the waves of a view read
 // both copies of the volume, whose L2 working set then doubled (256^3 cone forward
 // 18.9 -> 20.8 ms).
+// imgZ: the image with z fastest ([y][x][z]) for column packets (packet_cols = 1), whose
+// lanes share their xy path and differ in z only, or NULL.
 template <int DIM, int MODE, bool NEST = false>
 __device__ __forceinline__ void forward_one(const DevPlan& P, int32_t r, const float* img, const float* imgT,
-                                            float* sino, const float* wt = nullptr)
+                                            float* sino, const float* wt = nullptr, const float* imgZ = nullptr)
 {
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
     const float* base = img;
+    if constexpr (MODE != MODE_LIST && DIM == 3) {
+        if (imgZ != nullptr) {
+            base = imgZ;
+            R.st[0] = P.nz;
+            R.st[1] = P.nx * P.nz;
+            R.st[2] = 1;
+            imgT = nullptr;
+        }
+    }
     if constexpr (MODE != MODE_LIST) {
         if (imgT != nullptr) {
             const uint32_t per_view = (uint32_t)P.n_rows * (uint32_t)P.n_cols;
@@ -532,7 +543,7 @@ template <int DIM, int MODE, bool NEST>
 __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __restrict__ img,
                                                      const float* __restrict__ imgT, float* __restrict__ sino,
                                                      uint32_t nblocks, const float* __restrict__ wt,
-                                                     int64_t wt_stride)
+                                                     int64_t wt_stride, const float* __restrict__ imgZ)
 {
     uint32_t blk = blockIdx.x;
     if (P.xcd_remap) {
@@ -543,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevPlan P, const float* __re
     if (r < 0) return;
     const int64_t b = blockIdx.y;
     forward_one<DIM, MODE, NEST>(P, r, img + b * P.n_units, imgT, sino + b * P.n_rays,
-                           wt != nullptr ? wt + b * wt_stride : nullptr);
+                           wt != nullptr ? wt + b * wt_stride : nullptr, imgZ);
 }
 
 // ------------------------------------------------------------------ batched (several plans)
@@ -705,6 +716,25 @@ __global__ __launch_bounds__(kBlock) void k_transpose_xy(const float* __restrict
     for (int32_t xx = ty; xx < 32; xx += kBlock / 32) {
         const int32_t x = x0 + xx, y = y0 + tx;
         if (y < ny && x < nx) out[slab + (int64_t)x * ny + y] = tile[tx][xx];
+    }
+}
+
+// out[y][x][z] = in[z][y][x] (one y per block row of tiles: 32 z x 32 x)
+__global__ __launch_bounds__(kBlock) void k_transpose_zfast(const float* __restrict__ in, float* __restrict__ out,
+                                                             int32_t nx, int32_t ny, int32_t nz, int32_t ztiles)
+{
+    __shared__ float tile[32][33];
+    const int32_t y = blockIdx.y / ztiles;
+    const int32_t z0 = (blockIdx.y - y * ztiles) * 32, x0 = blockIdx.x * 32;
+    const int32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int32_t zz = ty; zz < 32; zz += kBlock / 32) {
+        const int32_t z = z0 + zz, x = x0 + tx;
+        if (z < nz && x < nx) tile[zz][tx] = in[((int64_t)z * ny + y) * nx + x];
+    }
+    __syncthreads();
+    for (int32_t xx = ty; xx < 32; xx += kBlock / 32) {
+        const int32_t x = x0 + xx, z = z0 + tx;
+        if (z < nz && x < nx) out[((int64_t)y * nx + x) * nz + z] = tile[tx][xx];
     }
 }
 
@@ -903,11 +933,27 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
     const uint32_t nb = (uint32_t)nb64;
     const uint32_t grid = P.xcd_remap ? (nb + 7u) / 8u * 8u : nb;
     // the walk's form (see walk()): chosen per plan
-    auto launch = [&](dim3 g, const float* im, const float* imT, float* sn, const float* w,
-                      int64_t ws) -> xrt_status {
-        return P.nest_z ? dispatch<FwdNestK>(P, g, s, im, imT, sn, nb, w, ws)
-                        : dispatch<FwdK>(P, g, s, im, imT, sn, nb, w, ws);
+    // (column packets take the flat form: their lanes' z slopes differ, so the nested
+    // form's inner loop would end at a different slab in every lane)
+    auto launch = [&](dim3 g, const float* im, const float* imT, float* sn, const float* w, int64_t ws,
+                      const float* imZ = nullptr) -> xrt_status {
+        return P.nest_z && P.packet_cols != 1 ? dispatch<FwdNestK>(P, g, s, im, imT, sn, nb, w, ws, imZ)
+                                              : dispatch<FwdK>(P, g, s, im, imT, sn, nb, w, ws, imZ);
     };
+    if (P.dim == 3 && P.packet_cols == 1 && p->d_imgZ != nullptr) {
+        for (int b = 0; b < batch; ++b) {
+            const float* im = img + (int64_t)b * P.n_units;
+            const int32_t ztiles = (P.nz + 31) / 32;
+            hipLaunchKernelGGL(k_transpose_zfast, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ztiles * P.ny)),
+                               dim3(kBlock), 0, s, im, p->d_imgZ, P.nx, P.ny, P.nz, ztiles);
+            xrt_status st = hip_fail(hipGetLastError(), "z-fastest transpose launch");
+            if (st != XRT_OK) return st;
+            st = launch(dim3(grid, 1u), im, (const float*)nullptr, sino + (int64_t)b * P.n_rays,
+                        wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr, (int64_t)0, p->d_imgZ);
+            if (st != XRT_OK) return st;
+        }
+        return XRT_OK;
+    }
     // one launch over the batch without the y-fastest copy (which holds one image) where
     // there is none, or for a batch of 2D images (small, so the copies would cost more
     // launches than they save); the values read are the same either way

@@ -14,7 +14,9 @@ import tempfile
 
 import numpy as np
 
-CANDIDATES = [(pc, xr) for pc in (0, 64, 32, 16) for xr in (0, 1)]
+# packet_cols 1 (column packets: 64 rows of one detector column, which share their xy path,
+# reading a z-fastest copy of the volume) applies to 3D plans only
+CANDIDATES = [(pc, xr) for pc in (0, 64, 32, 16, 1) for xr in (0, 1)]
 
 
 def cache_path() -> str:
@@ -98,7 +100,8 @@ def autotune(plan, img, path: str | None = None, repeats: int = 3, force: bool =
             return dict(hit, cached=True)
     out = torch.empty(tuple(plan.sino_shape), dtype=torch.float32, device=img.device)
     table = {}
-    for pc, xr in CANDIDATES:
+    cands = [c for c in CANDIDATES if c[0] != 1 or len(plan.image_shape) == 3]
+    for pc, xr in cands:
         plan.set_tuning(pc, xr)
         plan.forward(img, out=out)
         ts = []
@@ -112,7 +115,7 @@ def autotune(plan, img, path: str | None = None, repeats: int = 3, force: bool =
         table[f"{pc}x{xr}"] = float(np.median(ts))
         if log:
             log(f"[tune] packet_cols {pc} xcd_remap {xr}: {table[f'{pc}x{xr}']:.3f} ms")
-    best = min(CANDIDATES, key=lambda c: table[f"{c[0]}x{c[1]}"])
+    best = min(cands, key=lambda c: table[f"{c[0]}x{c[1]}"])
     choice = {"packet_cols": best[0], "xcd_remap": best[1]}
     plan.set_tuning(**choice)
     cache[sig] = dict(choice, ms=table[f"{best[0]}x{best[1]}"], table=table)

@@ -11,7 +11,7 @@ from tests.helpers import assert_within_bar, forward_bar, small_scans
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-SHAPES = [(0, 0), (0, 1), (64, 0), (32, 1), (16, 0), (16, 1)]
+SHAPES = [(0, 0), (0, 1), (64, 0), (32, 1), (16, 0), (16, 1), (1, 0), (1, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +47,7 @@ def test_launch_shapes_give_identical_results(X, name):
 def test_tuning_rejects_bad_values(X):
     grid, scan = {n: (g, s) for n, g, s in small_scans()}["cone_flat"]
     plan = X.Plan(grid, scan)
-    for pc, xr in ((48, 0), (32, 2), (-1, 0)):
+    for pc, xr in ((48, 0), (32, 2), (-1, 0), (2, 0)):
         with pytest.raises(X.XrtError) as e:
             plan.set_tuning(pc, xr)
         assert e.value.status == -1
