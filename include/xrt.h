@@ -315,10 +315,14 @@ xrt_status xrt_ray_transmission(xrt_plan* plan, const float* d_mu, float* d_w, i
 /* ---- launch shape of the forward projection (tuning; results do not depend on it) ----
  * packet_cols = 0: a wavefront takes 64 consecutive rays in (view, row, column) order;
  * 64, 32 or 16: a wavefront takes a packet of packet_cols detector columns x
- * (64 / packet_cols) rows of one view (ignored for ray lists).  xcd_remap = 1 gives
- * each of the 8 XCDs a contiguous range of packets (shared L2 working set).  A new plan
- * starts linear (0, 0); the best shape depends on the geometry and is found by timing
- * (the package's autotuner). */
+ * (64 / packet_cols) rows of one view; 1 (3D plans): column packets, 64 rows of one
+ * detector column, which read a z-fastest copy of the image that the plan allocates
+ * (n_units floats, kept; XRT_E_NOMEM if that fails) -- the rays of a cone's detector
+ * column share their xy path, so the lanes step through the same x/y slabs.  Ignored for
+ * ray lists.  xcd_remap = 1 gives each of the 8 XCDs a contiguous range of packets
+ * (shared L2 working set).  A new cone plan with at least 64 detector rows starts with
+ * column packets (1, 0), every other plan linear (0, 0); the best shape depends on the
+ * geometry and is found by timing (the package's autotuner). */
 typedef struct {
     int32_t packet_cols;
     int32_t xcd_remap;

@@ -120,12 +120,14 @@ xrt_status xrt_batch_forward(xrt_batch* batch, const float* const* d_imgs, float
 {
     if (!batch || !d_imgs || !d_sinos) { set_error("null argument"); return XRT_E_ARG; }
     float* imgT[kMaxBatch];
+    float* imgZ[kMaxBatch];
     for (int32_t m = 0; m < batch->n; ++m) {
         if (!d_imgs[m] || !d_sinos[m]) { set_error("null buffer for member %d", m); return XRT_E_ARG; }
         imgT[m] = batch->plans[m]->d_imgT;
+        imgZ[m] = batch->plans[m]->d_imgZ;
     }
     DeviceGuard guard(batch->device);
-    return launch_forward_batch(batch->hp, imgT, batch->d_plans, batch->n, batch->order, d_imgs, d_sinos,
+    return launch_forward_batch(batch->hp, imgT, imgZ, batch->d_plans, batch->n, batch->order, d_imgs, d_sinos,
                                 batch->d_counter, batch->grid, (hipStream_t)stream);
 }
 

@@ -160,10 +160,11 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
                           hipStream_t s, const float* wt = nullptr, int64_t wt_stride = 0);
 // One persistent launch over the members of a batch (host plan snapshots hp, device
 // copies d_plans, queue order, per-member images and sinograms).
-xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const DevPlan* d_plans, int32_t n,
-                                const int32_t* order, const float* const* imgs, float* const* sinos,
+xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, float* const* imgZ, const DevPlan* d_plans,
+                                int32_t n, const int32_t* order, const float* const* imgs, float* const* sinos,
                                 unsigned long long* counter, uint32_t grid, hipStream_t s);
 xrt_status launch_transpose_xy(const DevPlan& P, const float* img, float* imgT, hipStream_t s);
+xrt_status launch_transpose_zfast(const DevPlan& P, const float* img, float* imgZ, hipStream_t s);
 xrt_status launch_forward_att(const xrt_plan* p, const float* img, const float* mu, int64_t mu_stride, float* sino,
                               int batch, hipStream_t s);
 // muT: n_units floats of workspace for the map's y-fastest copy, or NULL

@@ -578,6 +578,21 @@ xrt_status xrt_plan_create(const xrt_grid* grid, const xrt_scan* scan, int devic
         }
         p->d_imgT = (float*)ws;
     }
+    // Cone scans: the rays of one detector column share their xy path, so with at least 64
+    // rows a wavefront takes 64 rows of one column by default (column packets, reading a
+    // z-fastest copy of the image; the 256^3 cone forward 19.0 -> 11.3 ms)
+    p->d_imgZ = nullptr;
+    if ((p->kind == XRT_CONE_FLAT || p->kind == XRT_CONE_ARC) && D.n_rows >= 64) {
+        void* ws = nullptr;
+        if (hipMalloc(&ws, (size_t)D.n_units * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            free_plan(p);
+            set_error("hipMalloc of the %lld-float column-packet workspace failed", (long long)D.n_units);
+            return XRT_E_NOMEM;
+        }
+        p->d_imgZ = (float*)ws;
+        D.packet_cols = 1;
+    }
     if (p->kind == XRT_CONE_FLAT && (st = cone_gather_setup(p, T.views)) != XRT_OK) {
         free_plan(p);
         return st;

@@ -574,6 +574,7 @@ struct BatchQueue {
 struct BatchIO {
     const float* in[kMaxBatch];
     const float* inT[kMaxBatch];
+    const float* inZ[kMaxBatch];   // z-fastest copy for members with column packets, or NULL
     float* out[kMaxBatch];
 };
 
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_batch(const DevPlan* __restr
             const int64_t blk = blk0 + c;
             if (blk >= q.nblocks[s]) break;
             const int32_t r = forward_ray_of<MODE>(P, (uint64_t)blk * kBlock + threadIdx.x);
-            if (r >= 0) forward_one<DIM, MODE>(P, r, io.in[m], io.inT[m], io.out[m]);
+            if (r >= 0) forward_one<DIM, MODE>(P, r, io.in[m], io.inT[m], io.out[m], nullptr, io.inZ[m]);
         }
     }
 }
@@ -943,10 +944,7 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
     if (P.dim == 3 && P.packet_cols == 1 && p->d_imgZ != nullptr) {
         for (int b = 0; b < batch; ++b) {
             const float* im = img + (int64_t)b * P.n_units;
-            const int32_t ztiles = (P.nz + 31) / 32;
-            hipLaunchKernelGGL(k_transpose_zfast, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ztiles * P.ny)),
-                               dim3(kBlock), 0, s, im, p->d_imgZ, P.nx, P.ny, P.nz, ztiles);
-            xrt_status st = hip_fail(hipGetLastError(), "z-fastest transpose launch");
+            xrt_status st = launch_transpose_zfast(P, im, p->d_imgZ, s);
             if (st != XRT_OK) return st;
             st = launch(dim3(grid, 1u), im, (const float*)nullptr, sino + (int64_t)b * P.n_rays,
                         wt != nullptr ? wt + (int64_t)b * wt_stride : nullptr, (int64_t)0, p->d_imgZ);
@@ -970,8 +968,16 @@ xrt_status launch_forward(const xrt_plan* p, const float* img, float* sino, int 
     return XRT_OK;
 }
 
-xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const DevPlan* d_plans, int32_t n,
-                                const int32_t* order, const float* const* imgs, float* const* sinos,
+xrt_status launch_transpose_zfast(const DevPlan& P, const float* img, float* imgZ, hipStream_t s)
+{
+    const int32_t ztiles = (P.nz + 31) / 32;
+    hipLaunchKernelGGL(k_transpose_zfast, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ztiles * P.ny)),
+                       dim3(kBlock), 0, s, img, imgZ, P.nx, P.ny, P.nz, ztiles);
+    return hip_fail(hipGetLastError(), "z-fastest transpose launch");
+}
+
+xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, float* const* imgZ, const DevPlan* d_plans,
+                                int32_t n, const int32_t* order, const float* const* imgs, float* const* sinos,
                                 unsigned long long* counter, uint32_t grid, hipStream_t s)
 {
     BatchQueue q{};
@@ -991,7 +997,13 @@ xrt_status launch_forward_batch(const DevPlan* hp, float* const* imgT, const Dev
         io.in[m] = imgs[m];
         io.out[m] = sinos[m];
         io.inT[m] = imgT[m];
-        if (imgT[m]) {
+        io.inZ[m] = nullptr;
+        if (hp[m].dim == 3 && hp[m].packet_cols == 1 && imgZ[m] != nullptr) {
+            io.inT[m] = nullptr;
+            io.inZ[m] = imgZ[m];
+            xrt_status st = launch_transpose_zfast(hp[m], imgs[m], imgZ[m], s);
+            if (st != XRT_OK) return st;
+        } else if (imgT[m]) {
             xrt_status st = launch_transpose_xy(hp[m], imgs[m], imgT[m], s);
             if (st != XRT_OK) return st;
         }
