@@ -334,18 +334,28 @@ xrt_status cone_gather_setup(xrt_plan* p, const std::vector<ViewGeom>& views)
     // tau = h / rho with rho = |E + u B| <= sqrt(sdd^2 + u_max^2); a voxel's rows have
     // v = (z - Sz)/tau over its z range and the pixel's h interval [h_in, h_in + diag],
     // so their spread is at most rho (dz / h_min + |z - Sz|_max diag / h_min^2).
+    // A voxel whose shadow reaches the detector has a point with |v| <= vabs (the rows'
+    // largest |v|), so |z - Sz| <= vabs tau_max + dz over the whole voxel, tau = h / rho <=
+    // hmax / sdd (h: horizontal distance from the source, hmax its largest value over the
+    // image box); voxels whose shadows miss the detector add nothing whatever the bound,
+    // which matters for helical scans, whose sources travel far beyond the detector's band.
     {
-        const double umax = std::fabs(D.ubase) + (D.n_cols - 1) * D.du;
+        const double umax = std::fmax(std::fabs(D.ubase), std::fabs(D.ubase + (D.n_cols - 1) * D.du));
         const double rho = std::sqrt(D.sdd * D.sdd + umax * umax);
         const double bx0 = D.px0, bx1 = D.px0 + D.nx * D.pdx, by1 = D.py0, by0 = D.py0 - D.ny * D.pdy;
         const double zhi = D.pz0, zlo = D.pz0 - D.nz * D.pdz;
-        double hmin = INFINITY, zrel = 0.0;
+        double hmin = INFINITY, hmax = 0.0, zrel = 0.0;
         for (const ViewGeom& V : views) {
             const double ddx = std::fmax(std::fmax(bx0 - V.A[0], V.A[0] - bx1), 0.0);
             const double ddy = std::fmax(std::fmax(by0 - V.A[1], V.A[1] - by1), 0.0);
             hmin = std::fmin(hmin, std::sqrt(ddx * ddx + ddy * ddy));
+            const double fx = std::fmax(std::fabs(bx0 - V.A[0]), std::fabs(bx1 - V.A[0]));
+            const double fy = std::fmax(std::fabs(by0 - V.A[1]), std::fabs(by1 - V.A[1]));
+            hmax = std::fmax(hmax, std::sqrt(fx * fx + fy * fy));
             zrel = std::fmax(zrel, std::fmax(std::fabs(zhi - V.A[2]), std::fabs(zlo - V.A[2])));
         }
+        const double vabs = std::fmax(std::fabs(D.vbase), std::fabs(D.vbase + (D.n_rows - 1) * D.dv));
+        zrel = std::fmin(zrel, (vabs * hmax / D.sdd + D.pdz) * (1.0 + 1e-9));
         const double diag = std::sqrt(D.pdx * D.pdx + D.pdy * D.pdy);
         const double spread = rho * (D.pdz / hmin + zrel * diag / (hmin * hmin)) / D.dv;
         const double nr = std::floor(spread + 1e-6) + 1.0;
