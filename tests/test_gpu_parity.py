@@ -308,3 +308,26 @@ def test_cone_256_sampled_parity(xrt):
     lhs = float((torch.from_numpy(got.reshape(plan.sino_shape)).to(dev()).double() * w.double()).sum())
     rhs = float((dimg.double() * Atw).sum())
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+# ------------------------------------------------------------------ the paper's closed-form ranges
+
+@pytest.mark.parametrize("d3", [False, True])
+def test_hit_lists_equal_the_paper_ranges(xrt, d3):
+    """Case-1 rays on the paper's unit grid: the kernel's hit list of every ray, grouped
+    by i, is the paper's range of valid j (and k) for that i (eqs. restriction_j,
+    restriction_j_3D, restriction_k_3D_1), with the length C_up - C_low (eqs.
+    range_length, range_length_3D) to FP32 rounding."""
+    from tests.test_oracle_ranges import _generic_case1_rays, _range_dict
+    dims = (12, 9, 10) if d3 else (14, 10)
+    g, rays = _generic_case1_rays(d3, 400, 53 + d3, dims, 5.0)
+    rows = gpu_hits(xrt, g, dict(kind="raylist3d" if d3 else "raylist2d", rays=np.array(rays)), eps=0.0)
+    nx = g["nx"]
+    for r, (gi, gl) in zip(rays, rows):
+        ref = _range_dict(g, r, d3)
+        for i in range(nx):
+            sel = gi % nx == i
+            want = sorted(I for I in ref if I % nx == i)
+            assert list(gi[sel]) == want, f"ray {r} slab i={i}"
+            np.testing.assert_allclose(gl[sel], [ref[I] for I in want], rtol=2e-6, atol=1e-6,
+                                       err_msg=f"ray {r} slab i={i}")
