@@ -105,6 +105,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64
 }
 
 constexpr int32_t kOutOfRange = (int32_t)0xFFFFFFF0u;
+// Where a block of 64 voxels lies against the source height Sz: every voxel above it
+// (z - Sz >= 0 on the bottom face), every voxel below it (z - Sz <= 0 on the top face), or
+// mixed.  Rays leave the source at parameters tau > 0, so only rows with v > 0 can hit a
+// voxel above and only rows with v < 0 a voxel below: there the order of the two face
+// parameters rel / v and of the two row bounds is known, and the min / max that sort
+// them drop out.
+constexpr int32_t kAbove = 0, kBelow = 1, kMixed = 2;
 // widening of candidate row ranges (in bins); column ranges, which come from the
 // hardware reciprocal's estimate (relative error below 2^-20; 2^-24.4 measured on gfx950),
 // are widened by the plan's uslack instead
@@ -181,170 +188,231 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if constexpr (!CULL) zb0[q] = zb0[q] - sz0;
     }
 
-    const int32_t slot = lane & ((1 << lg_slots) - 1), vlane = lane >> lg_slots;
-    for (int32_t v0 = 0; v0 < P.n_views; v0 += 64 >> lg_slots)
-        for (int32_t pass = 0;; ++pass) {
-            // this lane's view: detector columns whose rays can cross the pixel, from u of
-            // the four corners seen from the source, u = sdd^2 ((P - S).B) / ((P - S).E);
-            // recomputed per pass so that none of it stays live across the voxel loop
-            const int32_t v = v0 + vlane;
-            const bool vok = v < P.n_views;
-            const ViewGeom& V = P.views[vok ? v : P.n_views - 1];
-            const double Sx = V.A[0], Sy = V.A[1];
-            const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
-            const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
-            double umin = kInf, umax = -kInf;
+    // Circular scans: the class of each block against sz0 is fixed for the whole scan.
+    // When the wave's blocks are a run above sz0 followed by a run below it (every valid
+    // lane's voxel; lanes past the volume compute values that are never stored), the
+    // voxel loop is compiled for that split; otherwise, and for helical scans, every
+    // block takes the general form.  Below sz0 needs z - Sz < 0 on the top face when the
+    // detector has a row with v = 0 (that row's plane z = Sz belongs to a voxel whose top
+    // face it is).
+    int32_t split = -1;
+    if constexpr (!CULL) {
+        int32_t m = 0;
+        bool ok = true;
 #pragma unroll
-            for (int cnr = 0; cnr < 4; ++cnr) {
-                const double px = (cnr & 1) ? ax1 : ax0, py = (cnr & 2) ? ay1 : ay0;
-                const double u = sdd2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
-                umin = fmin(umin, u);
-                umax = fmax(umax, u);
-            }
-            const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
-            const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
-            const int32_t cb = c0 + (pass << lg_slots);
-            if (__builtin_amdgcn_ballot_w64(vok && cb <= c1) == 0) break;
-            // C_low / C_up of the pixel in xy, shared by every ray of column c
-            const int32_t c = cb + slot;
-            bool ok = vok && c <= c1;
-            double tin = -kInf, tout = kInf;
-            if (ok) {
-                const double u = fma((double)c, P.du, P.ubase);
-                axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
-                axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
-                ok = tin < tout;
-            }
-            const uint64_t live = __builtin_amdgcn_ballot_w64(ok);
-            if (ok) {
-                const int32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
-                R.tin[at] = tin;
-                R.tout[at] = tout;
-                // 1/tau in row bins for the candidate rows: refined, so that a row range of
-                // a few hundred bins stays within the rows' 1e-7-bin slack
-                R.sin[at] = rcp_full(tin) * idv;
-                R.sout[at] = rcp_full(tout) * idv;
-                R.sz[at] = V.A[2];
-                R.g[at] = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
-                if constexpr (CULL && KB == 4) {
-                    // heights z = Sz + tau v over tau in (tin, tout) and v in [vmin, vmax]
-                    // (bilinear: extremes at the corners), widened by a hundredth of a
-                    // unit; voxel k spans z in (pz0 - (k + 1) dz, pz0 - k dz]
-                    const double zlo = V.A[2] + fmin(tin * vmin, tout * vmin) - 0.01 * P.pdz;
-                    const double zhi = V.A[2] + fmax(tin * vmax, tout * vmax) + 0.01 * P.pdz;
-                    R.klo[at] = (int32_t)floor(fmin(fmax((P.pz0 - zhi) * idz, -2.0), (double)P.nz + 1.0));
-                    R.khi[at] = (int32_t)floor(fmin(fmax((P.pz0 - zlo) * idz, -2.0), (double)P.nz + 1.0));
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int32_t nrec = __builtin_popcountll(live);
-            for (int32_t e = 0; e < nrec; ++e) {
-                const double tin_ = R.tin[e], tout_ = R.tout[e], sin_ = R.sin[e], sout = R.sout[e], Sz = R.sz[e];
-                const int32_t gcol4 = R.g[e];
-                // C_up - C_low of row r in the voxel between z offsets rel0 < rel1: positive
-                // iff C_low < C_up (hit), else finite and non-positive (lanes past the
-                // volume, k >= nz, compute values that are never stored)
-                auto len = [&](int32_t r, double rel0, double rel1) {
-                    double lo = tin_, hi = tout_;
-                    if (ZR && r == zero_row) {
-                        if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
-                    } else {
-                        const double iv = s_iv[r];
-                        const double t0 = rel0 * iv, t1 = rel1 * iv;
-                        lo = fmax(lo, fmin(t0, t1));
-                        hi = fmin(hi, fmax(t0, t1));
-                    }
-                    return hi - lo;
-                };
-                // per voxel q of the lane: rows r0 and r0 + 1 (one 8-byte load, out of range
-                // when neither row is hit; a row that is not hit contributes 0), then the
-                // rows beyond where some shadow reaches them
-                int32_t r0[KB];
-                double l0[KB], l1[KB];
-                float g0[KB], g1[KB];
-                bool more[KB];
-                auto head = [&](int q) {
-                    // first candidate row: the smallest v = rel / tau of the voxel over
-                    // tau in (tin, tout), in bin units
-                    const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
-                    const double vlo = fmin(fma(rel0, sin_, vb_lo), fma(rel0, sout, vb_lo));
-                    // rows outside the voxel's range fail C_low < C_up below on their own
-                    // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
-                    r0[q] = min(max((int32_t)ceil(vlo), 0), P.n_rows);
-                    const double vhi = fmax(fma(rel1, sin_, vb_hi), fma(rel1, sout, vb_hi));
-                    more[q] = NR > 2 && vhi >= (double)(r0[q] + 2);
-                    if constexpr (CULL) {
-                        // rows past the detector are zero padding; a voxel whose rows all
-                        // lie above the first row (by half a bin, far beyond the error of
-                        // the estimates) has no hit in rows r0 = 0 ..
-                        const int32_t k = kbase + 64 * q;
-                        const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5 + kRangeSlack;
-                        if (__builtin_amdgcn_ballot_w64(any) == 0) return false;
-                    }
-                    l0[q] = len(r0[q], rel0, rel1);
-                    l1[q] = len(r0[q] + 1, rel0, rel1);
-                    const bool h0 = l0[q] > 0.0, h1 = l1[q] > 0.0;
-                    const int32_t off = h0 || h1 ? gcol4 + 4 * r0[q] : kOutOfRange;
-                    const uint32_t a = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off, 0, 0);
-                    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off + 4, 0, 0);
-                    g0[q] = h0 ? __builtin_bit_cast(float, a) : 0.0f;
-                    g1[q] = h1 ? __builtin_bit_cast(float, b) : 0.0f;
-                    return true;
-                };
-                auto body = [&](int q) {
-                    acc[q] = fma((double)g0[q], l0[q], acc[q]);
-                    acc[q] = fma((double)g1[q], l1[q], acc[q]);
-                };
-                // only where some lane's shadow spans more than one bin (whole waves skip it
-                // often enough that evaluating it always is slower)
-                auto tail = [&](int q) {
-                    if (NR > 2 && more[q]) {
-                        const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
-#pragma unroll
-                        for (int ei = 2; ei < NR; ++ei) {
-                            const int32_t r = r0[q] + ei;
-                            const double le = len(r, rel0, rel1);
-                            // a row that is not hit reads 0 (out of range)
-                            const float ge = __builtin_bit_cast(
-                                float, __builtin_amdgcn_raw_buffer_load_b32(
-                                           gsrc, le > 0.0 ? gcol4 + 4 * r : kOutOfRange, 0, 0));
-                            acc[q] = fma((double)ge, le, acc[q]);
-                        }
-                    }
-                };
-                if constexpr (CULL) {
-                    // helical scans: most voxels of a record are culled, first a block of 64
-                    // that the record's rays cannot reach (scalar test), then by the vote in
-                    // head(); a block that remains is done in full
-                    // (with 4 voxels per lane; shorter chunks rely on the vote alone)
-                    const int32_t klo = KB == 4 ? __builtin_amdgcn_readfirstlane(R.klo[e]) : -2;
-                    const int32_t khi = KB == 4 ? __builtin_amdgcn_readfirstlane(R.khi[e]) : P.nz + 1;
-#pragma unroll
-                    for (int q = 0; q < KB; ++q) {
-                        const int32_t k0 = kfirst + 64 * q;
-                        if (khi >= k0 && klo <= k0 + 63 && head(q)) {
-                            body(q);
-                            tail(q);
-                        }
-                    }
-                } else {
-                    // the loads of every voxel of the lane in flight together
-#pragma unroll
-                    for (int q = 0; q < KB; ++q) head(q);
-#pragma unroll
-                    for (int q = 0; q < KB; ++q) body(q);
-#pragma unroll
-                    for (int q = 0; q < KB; ++q) tail(q);
-                }
-            }
-            // every lane has read the records before the next pass rewrites them
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = 0; q < KB; ++q) {
+            const uint64_t valid = __builtin_amdgcn_ballot_w64(kbase + 64 * q < P.nz);
+            const double rel1 = zb0[q], rel0 = rel1 - P.pdz;
+            const bool above = (__builtin_amdgcn_ballot_w64(!(rel0 >= 0.0)) & valid) == 0;
+            const bool below = (__builtin_amdgcn_ballot_w64(!(ZR ? rel1 < 0.0 : rel1 <= 0.0)) & valid) == 0;
+            if (above && m == q)
+                m = q + 1;
+            else if (!below)
+                ok = false;
         }
+        split = ok ? m : -1;
+    }
+    auto run = [&](auto S) {
+        constexpr int32_t kSplit = decltype(S)::value;
+        // class of block q (a constant once the loops over q are unrolled)
+        auto cls_of = [](int q) { return kSplit < 0 ? kMixed : q < kSplit ? kAbove : kBelow; };
+
+        const int32_t slot = lane & ((1 << lg_slots) - 1), vlane = lane >> lg_slots;
+        for (int32_t v0 = 0; v0 < P.n_views; v0 += 64 >> lg_slots)
+            for (int32_t pass = 0;; ++pass) {
+                // this lane's view: detector columns whose rays can cross the pixel, from u of
+                // the four corners seen from the source, u = sdd^2 ((P - S).B) / ((P - S).E);
+                // recomputed per pass so that none of it stays live across the voxel loop
+                const int32_t v = v0 + vlane;
+                const bool vok = v < P.n_views;
+                const ViewGeom& V = P.views[vok ? v : P.n_views - 1];
+                const double Sx = V.A[0], Sy = V.A[1];
+                const double Ex = V.E[0], Ey = V.E[1], Bx = V.B[0], By = V.B[1];
+                const double ax0 = xa - Sx, ax1 = xb - Sx, ay0 = ya - Sy, ay1 = yb - Sy;
+                double umin = kInf, umax = -kInf;
+#pragma unroll
+                for (int cnr = 0; cnr < 4; ++cnr) {
+                    const double px = (cnr & 1) ? ax1 : ax0, py = (cnr & 2) ? ay1 : ay0;
+                    const double u = sdd2 * fma(px, Bx, py * By) * rcp_fast(fma(px, Ex, py * Ey));
+                    umin = fmin(umin, u);
+                    umax = fmax(umax, u);
+                }
+                const int32_t c0 = max(iceil(fma(umin - P.ubase, idu, -P.uslack), P.n_cols), 0);
+                const int32_t c1 = min(ifloor(fma(umax - P.ubase, idu, P.uslack), P.n_cols), P.n_cols - 1);
+                const int32_t cb = c0 + (pass << lg_slots);
+                if (__builtin_amdgcn_ballot_w64(vok && cb <= c1) == 0) break;
+                // C_low / C_up of the pixel in xy, shared by every ray of column c
+                const int32_t c = cb + slot;
+                bool ok = vok && c <= c1;
+                double tin = -kInf, tout = kInf;
+                if (ok) {
+                    const double u = fma((double)c, P.du, P.ubase);
+                    axis_interval(ax0, ax1, fma(u, Bx, Ex), true, tin, tout);
+                    axis_interval(ay0, ay1, fma(u, By, Ey), false, tin, tout);
+                    ok = tin < tout;
+                }
+                const uint64_t live = __builtin_amdgcn_ballot_w64(ok);
+                if (ok) {
+                    const int32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
+                    R.tin[at] = tin;
+                    R.tout[at] = tout;
+                    // 1/tau in row bins for the candidate rows: refined, so that a row range of
+                    // a few hundred bins stays within the rows' 1e-7-bin slack
+                    R.sin[at] = rcp_full(tin) * idv;
+                    R.sout[at] = rcp_full(tout) * idv;
+                    R.sz[at] = V.A[2];
+                    R.g[at] = (int32_t)(((int64_t)v * P.n_cols + c) * P.n_rows) * 4;
+                    if constexpr (CULL && KB == 4) {
+                        // heights z = Sz + tau v over tau in (tin, tout) and v in [vmin, vmax]
+                        // (bilinear: extremes at the corners), widened by a hundredth of a
+                        // unit; voxel k spans z in (pz0 - (k + 1) dz, pz0 - k dz]
+                        const double zlo = V.A[2] + fmin(tin * vmin, tout * vmin) - 0.01 * P.pdz;
+                        const double zhi = V.A[2] + fmax(tin * vmax, tout * vmax) + 0.01 * P.pdz;
+                        R.klo[at] = (int32_t)floor(fmin(fmax((P.pz0 - zhi) * idz, -2.0), (double)P.nz + 1.0));
+                        R.khi[at] = (int32_t)floor(fmin(fmax((P.pz0 - zlo) * idz, -2.0), (double)P.nz + 1.0));
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int32_t nrec = __builtin_popcountll(live);
+                for (int32_t e = 0; e < nrec; ++e) {
+                    const double tin_ = R.tin[e], tout_ = R.tout[e], sin_ = R.sin[e], sout = R.sout[e], Sz = R.sz[e];
+                    const int32_t gcol4 = R.g[e];
+                    // C_up - C_low of row r in the voxel between z offsets rel0 < rel1: positive
+                    // iff C_low < C_up (hit), else finite and non-positive (lanes past the
+                    // volume, k >= nz, compute values that are never stored).  Above Sz a row
+                    // with v > 0 crosses the faces at rel0 / v < rel1 / v; a row with v <= 0
+                    // (1/v <= 0, the zero row and the padding rows store 0) gets an upper end
+                    // <= 0 < tin, so a non-positive value as it should.  Below Sz likewise with
+                    // the faces swapped.  Hits get the same value as from the general form.
+                    auto len = [&](int32_t r, double rel0, double rel1, int32_t cls) {
+                        double lo = tin_, hi = tout_;
+                        if (cls == kAbove) {
+                            const double iv = s_iv[r];
+                            lo = fmax(lo, rel0 * iv);
+                            hi = fmin(hi, rel1 * iv);
+                        } else if (cls == kBelow) {
+                            const double iv = s_iv[r];
+                            lo = fmax(lo, rel1 * iv);
+                            hi = fmin(hi, rel0 * iv);
+                        } else if (ZR && r == zero_row) {
+                            if (!(rel0 < 0.0 && rel1 >= 0.0)) hi = lo;   // plane z = Sz not in (za, zb]
+                        } else {
+                            const double iv = s_iv[r];
+                            const double t0 = rel0 * iv, t1 = rel1 * iv;
+                            lo = fmax(lo, fmin(t0, t1));
+                            hi = fmin(hi, fmax(t0, t1));
+                        }
+                        return hi - lo;
+                    };
+                    // per voxel q of the lane: rows r0 and r0 + 1 (one 8-byte load, out of range
+                    // when neither row is hit; a row that is not hit contributes 0), then the
+                    // rows beyond where some shadow reaches them
+                    int32_t r0[KB];
+                    double l0[KB], l1[KB];
+                    float g0[KB], g1[KB];
+                    bool more[KB];
+                    auto head = [&](int q) {
+                        const int32_t cls = cls_of(q);
+                        // first candidate row: the smallest v = rel / tau of the voxel over
+                        // tau in (tin, tout), in bin units (1/tin > 1/tout > 0: above Sz the
+                        // smallest at tout, below it at tin, and the largest the other way)
+                        const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
+                        const double vlo = cls == kAbove   ? fma(rel0, sout, vb_lo)
+                                           : cls == kBelow ? fma(rel0, sin_, vb_lo)
+                                                           : fmin(fma(rel0, sin_, vb_lo), fma(rel0, sout, vb_lo));
+                        // rows outside the voxel's range fail C_low < C_up below on their own
+                        // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
+                        r0[q] = min(max((int32_t)ceil(vlo), 0), P.n_rows);
+                        const double vhi = cls == kAbove   ? fma(rel1, sin_, vb_hi)
+                                           : cls == kBelow ? fma(rel1, sout, vb_hi)
+                                                           : fmax(fma(rel1, sin_, vb_hi), fma(rel1, sout, vb_hi));
+                        more[q] = NR > 2 && vhi >= (double)(r0[q] + 2);
+                        if constexpr (CULL) {
+                            // rows past the detector are zero padding; a voxel whose rows all
+                            // lie above the first row (by half a bin, far beyond the error of
+                            // the estimates) has no hit in rows r0 = 0 ..
+                            const int32_t k = kbase + 64 * q;
+                            const bool any = k < P.nz && r0[q] < P.n_rows && vhi >= -0.5 + kRangeSlack;
+                            if (__builtin_amdgcn_ballot_w64(any) == 0) return false;
+                        }
+                        l0[q] = len(r0[q], rel0, rel1, cls);
+                        l1[q] = len(r0[q] + 1, rel0, rel1, cls);
+                        const bool h0 = l0[q] > 0.0, h1 = l1[q] > 0.0;
+                        const int32_t off = h0 || h1 ? gcol4 + 4 * r0[q] : kOutOfRange;
+                        const uint32_t a = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off, 0, 0);
+                        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off + 4, 0, 0);
+                        g0[q] = h0 ? __builtin_bit_cast(float, a) : 0.0f;
+                        g1[q] = h1 ? __builtin_bit_cast(float, b) : 0.0f;
+                        return true;
+                    };
+                    auto body = [&](int q) {
+                        acc[q] = fma((double)g0[q], l0[q], acc[q]);
+                        acc[q] = fma((double)g1[q], l1[q], acc[q]);
+                    };
+                    // only where some lane's shadow spans more than one bin (whole waves skip it
+                    // often enough that evaluating it always is slower)
+                    auto tail = [&](int q) {
+                        if (NR > 2 && more[q]) {
+                            const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
+#pragma unroll
+                            for (int ei = 2; ei < NR; ++ei) {
+                                const int32_t r = r0[q] + ei;
+                                const double le = len(r, rel0, rel1, cls_of(q));
+                                // a row that is not hit reads 0 (out of range)
+                                const float ge = __builtin_bit_cast(
+                                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                                               gsrc, le > 0.0 ? gcol4 + 4 * r : kOutOfRange, 0, 0));
+                                acc[q] = fma((double)ge, le, acc[q]);
+                            }
+                        }
+                    };
+                    if constexpr (CULL) {
+                        // helical scans: most voxels of a record are culled, first a block of 64
+                        // that the record's rays cannot reach (scalar test), then by the vote in
+                        // head(); a block that remains is done in full
+                        // (with 4 voxels per lane; shorter chunks rely on the vote alone)
+                        const int32_t klo = KB == 4 ? __builtin_amdgcn_readfirstlane(R.klo[e]) : -2;
+                        const int32_t khi = KB == 4 ? __builtin_amdgcn_readfirstlane(R.khi[e]) : P.nz + 1;
+#pragma unroll
+                        for (int q = 0; q < KB; ++q) {
+                            const int32_t k0 = kfirst + 64 * q;
+                            if (khi >= k0 && klo <= k0 + 63 && head(q)) {
+                                body(q);
+                                tail(q);
+                            }
+                        }
+                    } else {
+                        // the loads of every voxel of the lane in flight together
+#pragma unroll
+                        for (int q = 0; q < KB; ++q) head(q);
+#pragma unroll
+                        for (int q = 0; q < KB; ++q) body(q);
+#pragma unroll
+                        for (int q = 0; q < KB; ++q) tail(q);
+                    }
+                }
+                // every lane has read the records before the next pass rewrites them
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+    };
+    using std::integral_constant;
+    if (CULL || split < 0)
+        run(integral_constant<int32_t, -1>{});
+    else if (split == 0)
+        run(integral_constant<int32_t, 0>{});
+    else if (KB == 1 || split == 1)
+        run(integral_constant<int32_t, 1>{});
+    else if (KB == 2 || split == 2)
+        run(integral_constant<int32_t, 2>{});
+    else if (split == 3)
+        run(integral_constant<int32_t, 3>{});
+    else
+        run(integral_constant<int32_t, 4>{});
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
         const int32_t k = kbase + 64 * q;
