@@ -333,8 +333,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     double l0[KB], l1[KB];
                     float g0[KB], g1[KB];
                     bool more[KB];
-                    auto head = [&](int q) {
-                        const int32_t cls = cls_of(q);
+                    auto head = [&](int q, int32_t cls) {
                         // first candidate row: the smallest v = rel / tau of the voxel over
                         // tau in (tin, tout), in bin units (1/tin > 1/tout > 0: above Sz the
                         // smallest at tout, below it at tin, and the largest the other way)
@@ -372,13 +371,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     };
                     // only where some lane's shadow spans more than one bin (whole waves skip it
                     // often enough that evaluating it always is slower)
-                    auto tail = [&](int q) {
+                    auto tail = [&](int q, int32_t cls) {
                         if (NR > 2 && more[q]) {
                             const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
 #pragma unroll
                             for (int ei = 2; ei < NR; ++ei) {
                                 const int32_t r = r0[q] + ei;
-                                const double le = len(r, rel0, rel1, cls_of(q));
+                                const double le = len(r, rel0, rel1, cls);
                                 // a row that is not hit reads 0 (out of range)
                                 const float ge = __builtin_bit_cast(
                                     float, __builtin_amdgcn_raw_buffer_load_b32(
@@ -396,15 +395,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         for (int32_t kb = max(klo, kfirst); kb <= kstop; kb += 64) {
                             kq[0] = kb + lane;
                             zb0[0] = P.pz0 - (double)kq[0] * P.pdz;
-                            if (head(0)) {
-                                // lanes past the wave's voxels compute values never stored
-                                const bool mine = kq[0] < kend;
-                                const int32_t at = kq[0] - kfirst;
-                                acc[0] = mine ? s_acc[at] : 0.0;
-                                body(0);
-                                tail(0);
-                                if (mine) s_acc[at] = acc[0];
-                            }
+                            // the block's class against this record's source height (lanes
+                            // past the volume do not count), one copy of the block's code
+                            // per class
+                            const uint64_t valid = __builtin_amdgcn_ballot_w64(kq[0] < P.nz);
+                            const double rel1 = zb0[0] - Sz, rel0 = rel1 - P.pdz;
+                            const bool above = (__builtin_amdgcn_ballot_w64(!(rel0 >= 0.0)) & valid) == 0;
+                            const bool below =
+                                (__builtin_amdgcn_ballot_w64(!(ZR ? rel1 < 0.0 : rel1 <= 0.0)) & valid) == 0;
+                            auto block = [&](int32_t cls) {
+                                if (head(0, cls)) {
+                                    // lanes past the wave's voxels compute values never stored
+                                    const bool mine = kq[0] < kend;
+                                    const int32_t at = kq[0] - kfirst;
+                                    acc[0] = mine ? s_acc[at] : 0.0;
+                                    body(0);
+                                    tail(0, cls);
+                                    if (mine) s_acc[at] = acc[0];
+                                }
+                            };
+                            if (above)
+                                block(kAbove);
+                            else if (below)
+                                block(kBelow);
+                            else
+                                block(kMixed);
                         }
                         // the next record's blocks give these voxels to other lanes
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -414,19 +429,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         // shorter chunks: the fixed blocks, culled by the vote in head()
 #pragma unroll
                         for (int q = 0; q < KB; ++q) {
-                            if (head(q)) {
+                            if (head(q, kMixed)) {
                                 body(q);
-                                tail(q);
+                                tail(q, kMixed);
                             }
                         }
                     } else {
                         // the loads of every voxel of the lane in flight together
 #pragma unroll
-                        for (int q = 0; q < KB; ++q) head(q);
+                        for (int q = 0; q < KB; ++q) head(q, cls_of(q));
 #pragma unroll
                         for (int q = 0; q < KB; ++q) body(q);
 #pragma unroll
-                        for (int q = 0; q < KB; ++q) tail(q);
+                        for (int q = 0; q < KB; ++q) tail(q, cls_of(q));
                     }
                 }
                 // every lane has read the records before the next pass rewrites them
