@@ -138,18 +138,20 @@ constexpr int kWaves = kBlock / 64;
 // blocks follow each record's band [klo, khi] of reachable voxels: 64 consecutive voxels
 // from klo (lane = voxel - block start), with the wave's voxel sums in LDS -- the band,
 // about as tall as the detector's shadow, then takes 1.5 blocks on average instead of 2
-// fixed ones.  Every voxel adds its records in record order either way.  Without CULL (circular scans) every
-// source sits at the height sz0, and voxel heights are taken relative to it once.
+// fixed ones.  Every voxel adds its records in record order either way.  Without CULL
+// (circular scans) every source sits at the height sz0, and voxel heights are taken
+// relative to it once.
 // lg_slots: log2 of the column slots per view in one record pass (a bound on the
 // columns of a pixel's shadow, from the plan; wider shadows take further passes).
-// vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling); vb_lo,
-// vb_hi: row coordinate of v = 0 in bins, -vbase / dv, minus and plus the candidate
-// rows' slack of kRangeSlack bins (kernel arguments, so they stay in scalar registers).
+// vmin, vmax: range of the detector rows' v, idz = 1 / pdz (helical culling); vb_lo1,
+// vb_hi: row coordinate of v = 0 in bins, -vbase / dv, minus (plus one) and plus the
+// candidate rows' slack of kRangeSlack bins (kernel arguments, so they stay in scalar
+// registers).
 template <int KB, int NR, bool ZR, bool CULL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_cone_gather(
     DevPlan P, const float* __restrict__ gT, float* __restrict__ img, const double* __restrict__ inv_v,
     int32_t zero_row, int32_t nzc, int32_t nlogical, int32_t lg_slots, double vmin, double vmax, double idz,
-    double vb_lo, double vb_hi, double sz0)
+    double vb_lo1, double vb_hi, double sz0)
 {
     // 1/v of every row followed by NR entries 0 for rows past the detector (their z
     // interval (0, 0) lies before tin > 0, so they are never hit), then the per-wave
@@ -338,12 +340,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         // tau in (tin, tout), in bin units (1/tin > 1/tout > 0: above Sz the
                         // smallest at tout, below it at tin, and the largest the other way)
                         const double rel1 = CULL ? zb0[q] - Sz : zb0[q], rel0 = rel1 - P.pdz;
-                        const double vlo = cls == kAbove   ? fma(rel0, sout, vb_lo)
-                                           : cls == kBelow ? fma(rel0, sin_, vb_lo)
-                                                           : fmin(fma(rel0, sin_, vb_lo), fma(rel0, sout, vb_lo));
+                        // plus one: r0 = trunc(vlo + 1) is ceil(vlo), or one more where vlo is an
+                        // integer m -- that row then lies below the voxel's rows by the slack
+                        const double vlo1 = cls == kAbove   ? fma(rel0, sout, vb_lo1)
+                                            : cls == kBelow ? fma(rel0, sin_, vb_lo1)
+                                                            : fmin(fma(rel0, sin_, vb_lo1), fma(rel0, sout, vb_lo1));
                         // rows outside the voxel's range fail C_low < C_up below on their own
                         // (clamped so that r0 + NR - 1 stays inside the padded 1/v table)
-                        r0[q] = min(max((int32_t)ceil(vlo), 0), P.n_rows);
+                        r0[q] = min(max((int32_t)vlo1, 0), P.n_rows);
                         const double vhi = cls == kAbove   ? fma(rel1, sin_, vb_hi)
                                            : cls == kBelow ? fma(rel1, sout, vb_hi)
                                                            : fmax(fma(rel1, sin_, vb_hi), fma(rel1, sout, vb_hi));
@@ -731,11 +735,11 @@ xrt_status launch_kb(const xrt_plan* p, const float* gT, float* img, hipStream_t
     if (p->zero_row >= 0)
         hipLaunchKernelGGL((k_cone_gather<KB, NR, true, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack, sz0);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack + 1.0, vb + kRangeSlack, sz0);
     else
         hipLaunchKernelGGL((k_cone_gather<KB, NR, false, CULL>), dim3((unsigned)launched), dim3(kBlock), lds, s, P,
                            gT, img, (const double*)p->d_invwz, p->zero_row, nzc, (int32_t)nlog, p->gather_lgs,
-                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack, vb + kRangeSlack, sz0);
+                           vmin, vmax, 1.0 / P.pdz, vb - kRangeSlack + 1.0, vb + kRangeSlack, sz0);
     return hip_fail(hipGetLastError(), "gather kernel launch");
 }
 
