@@ -59,10 +59,16 @@ struct FwdVisit {
         acc = fma((double)p2, q2, acc);
         acc = fma((double)p3, q3, acc);
     }
-    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    // h2, h3: the walk's flags (the candidate may have a positive length); a candidate
+    // that cannot reads out of range (0).  In 3D the second candidate's load keeps its
+    // length test: issued after the lengths, the loads leave the previous slab's values
+    // time to arrive before they are summed (256^3 cone forward: both length tests
+    // 11.28 ms, both flags 11.49 ms -- the loads moved ahead and the sums waited --, this
+    // mix 11.06 ms)
+    __device__ __forceinline__ void two_h(int32_t I1, double l1, int32_t I2, double l2, bool h2)
     {
         const float f1 = load(I1);
-        const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
+        const float f2 = load(h2 ? I2 : kOutOfRange);
         consume();
         p1 = f1;
         p2 = f2;
@@ -71,12 +77,12 @@ struct FwdVisit {
         q2 = l2;
         q3 = 0.0;
     }
-    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
-                                          double l3)
+    __device__ __forceinline__ void three_h(int32_t I1, double l1, int32_t I2, double l2, bool h2, int32_t I3,
+                                            double l3, bool h3)
     {
         const float f1 = load(I1);
         const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
-        const float f3 = load(l3 > 0.0 ? I3 : kOutOfRange);
+        const float f3 = load(h3 ? I3 : kOutOfRange);
         consume();
         p1 = f1;
         p2 = f2;
@@ -107,10 +113,10 @@ struct FwdVisit2 {
         acc = fma((double)r1, s1, acc);
         acc = fma((double)r2, s2, acc);
     }
-    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    __device__ __forceinline__ void two_h(int32_t I1, double l1, int32_t I2, double l2, bool h2)
     {
         const float f1 = load(I1);
-        const float f2 = load(l2 > 0.0 ? I2 : kOutOfRange);
+        const float f2 = load(h2 ? I2 : kOutOfRange);
         acc = fma((double)p1, q1, acc);
         acc = fma((double)p2, q2, acc);
         p1 = r1;
@@ -122,7 +128,7 @@ struct FwdVisit2 {
         s1 = l1;
         s2 = l2;
     }
-    __device__ __forceinline__ void three(int32_t, double, int32_t, double, int32_t, double) {}
+    __device__ __forceinline__ void three_h(int32_t, double, int32_t, double, bool, int32_t, double, bool) {}
 };
 
 // FwdVisit for a batch in the lanes of a wavefront: every lane walks the same ray (the
@@ -147,10 +153,10 @@ struct FwdBatchVisit {
         acc = fma((double)p2, q2, acc);
         acc = fma((double)p3, q3, acc);
     }
-    __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
+    __device__ __forceinline__ void two_h(int32_t I1, double l1, int32_t I2, double l2, bool h2)
     {
         const float f1 = load(true, I1);
-        const float f2 = load(l2 > 0.0, I2);
+        const float f2 = load(h2, I2);
         consume();
         p1 = f1;
         p2 = f2;
@@ -159,12 +165,12 @@ struct FwdBatchVisit {
         q2 = l2;
         q3 = 0.0;
     }
-    __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
-                                          double l3)
+    __device__ __forceinline__ void three_h(int32_t I1, double l1, int32_t I2, double l2, bool h2, int32_t I3,
+                                            double l3, bool h3)
     {
         const float f1 = load(true, I1);
-        const float f2 = load(l2 > 0.0, I2);
-        const float f3 = load(l3 > 0.0, I3);
+        const float f2 = load(h2, I2);
+        const float f3 = load(h3, I3);
         consume();
         p1 = f1;
         p2 = f2;

@@ -197,6 +197,18 @@ struct wants_start : std::false_type {};
 template <class V>
 struct wants_start<V, std::void_t<decltype(&V::start)>> : std::true_type {};
 
+// A visitor with members two_h / three_h is also told, per later candidate, whether it can
+// have a positive length: the second of a slab's candidates iff some secondary crossing
+// lies in the slab (its length is then >= 0, 0 only where two crossings coincide), the
+// third iff both do (its length is then > 0).  The flags come from the crossing tests the
+// walk makes anyway, so a visitor that only needs "may be hit" skips a compare per
+// candidate; one that adds len * value gets the same sums (a flagged candidate of length
+// 0 adds 0).
+template <class V, class = void>
+struct wants_flags : std::false_type {};
+template <class V>
+struct wants_flags<V, std::void_t<decltype(&V::three_h)>> : std::true_type {};
+
 // Walk the chord slab by slab.  The visitor receives the candidate units of every slab
 // with their C_up - C_low in ray-parameter units: vis.two(I1, l1, I2, l2) (2D) or
 // vis.three(I1, l1, I2, l2, I3, l3) (3D), where I1 -- the unit the ray is in at slab
@@ -225,6 +237,18 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
     if (!setup_axes<DIM>(P, R, ax, tin, tout)) return;
     if constexpr (wants_start<Visit>::value) vis.start(tin);
     constexpr int32_t SC = Visit::kIndexScale;
+    auto emit2 = [&](int32_t I1, double l1, int32_t I2, double l2, bool h2) {
+        if constexpr (wants_flags<Visit>::value)
+            vis.two_h(I1, l1, I2, l2, h2);
+        else
+            vis.two(I1, l1, I2, l2);
+    };
+    auto emit3 = [&](int32_t I1, double l1, int32_t I2, double l2, bool h2, int32_t I3, double l3, bool h3) {
+        if constexpr (wants_flags<Visit>::value)
+            vis.three_h(I1, l1, I2, l2, h2, I3, l3, h3);
+        else
+            vis.three(I1, l1, I2, l2, I3, l3);
+    };
 
     int32_t I = 0;
 #pragma unroll
@@ -256,7 +280,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
             const double l2 = tx1 - tn1;
             const bool c1 = tn1 < tx1;
             const int32_t Iend = c1 ? I + sd1 : I;
-            vis.two(I, fmax(l1, 0.0), Iend, l2);
+            emit2(I, fmax(l1, 0.0), Iend, l2, c1);
             if (c1) {
                 m1 += sg1;
                 tn1 = (m1 - q1) * inv1;
@@ -270,7 +294,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
             const bool c1 = tn1 < tx1, c2 = tn2 < tx1;
             const int32_t Imid = I + (tn1 < tn2 ? sd1 : sd2);
             const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
-            vis.three(I, fmax(l1, 0.0), Imid, l2, Iend, l3);
+            emit3(I, fmax(l1, 0.0), Imid, l2, c1 || c2, Iend, l3, c1 && c2);
             if (c1) {
                 m1 += sg1;
                 tn1 = (m1 - q1) * inv1;
@@ -301,7 +325,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                 const double l2 = dt0 - r1;
                 const bool c1 = r1 < dt0;
                 const int32_t Iend = c1 ? I + sd1 : I;
-                vis.two(I, l1, Iend, l2);
+                emit2(I, l1, Iend, l2, c1);
                 r1 += c1 ? e1 : -dt0;
                 I = Iend + sd0;
             }
@@ -320,7 +344,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                     const bool c1 = r1 < dt0, c2 = r2 < dt0;
                     const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
                     const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
-                    vis.three(I, l1, Imid, l2, Iend, l3);
+                    emit3(I, l1, Imid, l2, c1 || c2, Iend, l3, c1 && c2);
                     r1 += c1 ? e1 : -dt0;
                     r2 += c2 ? e2 : -dt0;
                     I = Iend + sd0;
@@ -337,7 +361,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                         const double l2 = dt0 - r1;
                         const bool c1 = r1 < dt0;
                         const int32_t Iend = c1 ? I + sd1 : I;
-                        vis.two(I, l1, Iend, l2);
+                        emit2(I, l1, Iend, l2, c1);
                         r1 += c1 ? e1 : -dt0;
                         r2 -= dt0;
                         I = Iend + sd0;
@@ -350,7 +374,7 @@ XRT_HD void walk(const DevPlan& P, const Ray& R, Visit& vis)
                         const bool c1 = r1 < dt0, c2 = r2 < dt0;
                         const int32_t Imid = I + (r1 < r2 ? sd1 : sd2);
                         const int32_t Iend = I + (c1 ? sd1 : 0) + (c2 ? sd2 : 0);
-                        vis.three(I, l1, Imid, l2, Iend, l3);
+                        emit3(I, l1, Imid, l2, c1 || c2, Iend, l3, c1 && c2);
                         r1 += c1 ? e1 : -dt0;
                         r2 += c2 ? e2 : -dt0;
                         I = Iend + sd0;
