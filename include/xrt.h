@@ -149,7 +149,10 @@ xrt_status xrt_forward(xrt_plan* plan, const float* d_img, float* d_sino, int32_
                        void* stream);
 
 /* Adjoint: d_img[b][I] = sum_r d_sino[b][r] * len(r, I).  Overwrites d_img (the
- * library clears it with its own kernel first).  mode: xrt_adjoint_mode. */
+ * library clears it with its own kernel first).  mode: xrt_adjoint_mode.  The sinogram
+ * is expected finite: the cone gather multiplies the values of a voxel's candidate rows
+ * by lengths clamped at 0, so a NaN or infinity can also reach voxels next to those its
+ * ray crosses. */
 xrt_status xrt_adjoint(xrt_plan* plan, const float* d_sino, float* d_img, int32_t batch,
                        int32_t mode, void* stream);
 

@@ -365,13 +365,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         const int32_t off = h0 || h1 ? gcol4 + 4 * r0[q] : kOutOfRange;
                         const uint32_t a = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off, 0, 0);
                         const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(gsrc, off + 4, 0, 0);
-                        g0[q] = h0 ? __builtin_bit_cast(float, a) : 0.0f;
-                        g1[q] = h1 ? __builtin_bit_cast(float, b) : 0.0f;
+                        // a row that is not hit adds its value times a length clamped to
+                        // 0 (both rows out of range read 0)
+                        g0[q] = __builtin_bit_cast(float, a);
+                        g1[q] = __builtin_bit_cast(float, b);
                         return true;
                     };
                     auto body = [&](int q) {
-                        acc[q] = fma((double)g0[q], l0[q], acc[q]);
-                        acc[q] = fma((double)g1[q], l1[q], acc[q]);
+                        acc[q] = fma((double)g0[q], fmax(l0[q], 0.0), acc[q]);
+                        acc[q] = fma((double)g1[q], fmax(l1[q], 0.0), acc[q]);
                     };
                     // only where some lane's shadow spans more than one bin (whole waves skip it
                     // often enough that evaluating it always is slower)
