@@ -5,8 +5,11 @@ projection matrix; eq. range_length_3D gives each length).
 * Deep, narrow volumes (the oracle adjoint of every ray stays cheap) that take 2 voxels
   per lane (65 <= nz <= 128) and 4 voxels per lane (nz > 128, one and two z chunks),
   circular with and without a detector row at v = 0, with 3 to 8 candidate rows per
-  voxel, and helical with 2 and 4 voxels per lane (the 4-voxel helical kernel skips the
-  blocks of voxels no ray of a record reaches).
+  voxel, and helical with 2 and 4 voxels per lane (the 4-voxel helical kernel takes each
+  record's reachable band of voxels in blocks, each in the form of its class against
+  the record's source height).  Circular cases also cover the loops compiled for waves
+  whose blocks lie above and then below the source plane (split after 1 of 2 and 3 of 4
+  blocks; every block below with a v = 0 row) besides the general loop.
 * The 256^3 cone of the benchmark and a 512 x 512 x 256 helical member of the batched
   workload at full size: sampled voxels, each summed over every view from the rays of
   a window around its shadow, clipped against the voxel by the oracle's brute force.
@@ -59,6 +62,19 @@ DEEP = [
      _helix(24, 2, -80.0, 80.0, ncols=25, nrows=96, du=1.0, dv=0.5, u0=0.05, v0=0.0, sod=300.0, sdd=450.0), 4, 1),
     ("kb2_helical", dict(nx=12, ny=10, nz=100, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.2),
      _helix(20, 2, -60.0, 60.0, ncols=27, nrows=48, du=1.0, dv=1.0, u0=0.0, v0=0.0, sod=300.0, sdd=450.0), 2, 1),
+    # circular scans whose waves take the split loops: blocks of 64 voxels above the
+    # source plane, then below it (a block boundary on the plane z = 0)
+    ("kb2_split_above_below", dict(nx=12, ny=10, nz=128, dx=1.0, dy=1.0, dz=1.0, cx=0.3, cy=0.1, cz=0.0),
+     dict(kind="cone_flat", angles=np.linspace(0.05, 2 * PI, 20, endpoint=False), ncols=25, nrows=210, du=1.0,
+          dv=1.0, u0=0.0, v0=0.0, sod=100.0, sdd=150.0), 2, 0),
+    ("kb4_split_three_above", dict(nx=10, ny=12, nz=256, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=-0.3, cz=64.0),
+     dict(kind="cone_flat", angles=np.linspace(0.1, 2 * PI, 16, endpoint=False), ncols=27, nrows=540, du=1.0,
+          dv=1.0, u0=0.0, v0=0.0, sod=300.0, sdd=450.0), 4, 0),
+    # the whole volume below the source plane, with a detector row at v = 0: every block
+    # below (strictly: that row's plane z = Sz belongs to no voxel)
+    ("kb4_all_below_zero_row", dict(nx=12, ny=10, nz=160, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=-90.0),
+     dict(kind="cone_flat", angles=np.linspace(0.0, 2 * PI, 16, endpoint=False), ncols=25, nrows=601, du=1.0,
+          dv=1.0, u0=0.0, v0=0.0, sod=100.0, sdd=150.0), 4, 0),
 ]
 
 
