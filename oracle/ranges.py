@@ -34,21 +34,29 @@ def _open_integers(lo: float, hi: float, n: int):
     return [q for q in range(first, last + 1) if lo < q < hi]
 
 
-def case1_2d(nx: int, ny: int, s: float, phi: float):
-    """Units (j, i) -> length of the 2D ray (s, phi), phi in (0, pi/2), listed by i
-    (eq. restriction_j) with C_up - C_low (eq. range_length)."""
+def case1_2d_steps(nx: int, ny: int, s: float, phi: float):
+    """The steps of the 2D range computation for every i, as the paper's hand
+    computations of Test suite 1 list them: [(i, C_x, C_1, {j: (C_y, length)})]."""
     assert 0.0 < phi < math.pi / 2
     c, sn = math.cos(phi), math.sin(phi)
-    out = {}
+    steps = []
     for i in range(nx):
         cx = (i - nx / 2 + s * sn) / c
         c1 = ny / 2 - s * c - cx * sn
+        js = {}
         for j in _open_integers(c1 - math.tan(phi) - 1.0, c1, ny):
             cy = (ny / 2 - j - s * c) / sn
             c_low = max(cx, cy - 1.0 / sn)
             c_up = min(cx + 1.0 / c, cy)
-            out[(j, i)] = c_up - c_low
-    return out
+            js[j] = (cy, c_up - c_low)
+        steps.append((i, cx, c1, js))
+    return steps
+
+
+def case1_2d(nx: int, ny: int, s: float, phi: float):
+    """Units (j, i) -> length of the 2D ray (s, phi), phi in (0, pi/2), listed by i
+    (eq. restriction_j) with C_up - C_low (eq. range_length)."""
+    return {(j, i): ln for i, _, _, js in case1_2d_steps(nx, ny, s, phi) for j, (_, ln) in js.items()}
 
 
 def case1_2d_given_j(nx: int, ny: int, s: float, phi: float):
@@ -65,30 +73,43 @@ def case1_2d_given_j(nx: int, ny: int, s: float, phi: float):
     return out
 
 
-def case1_3d(nx: int, ny: int, nz: int, s1: float, s2: float, phi1: float, phi2: float):
-    """Units (k, j, i) -> length of the 3D ray (s1, s2, phi1, phi2), both angles in
-    (0, pi/2), listed by i (eqs. restriction_j_3D, restriction_k_3D_1) with
-    C_up - C_low (eq. range_length_3D)."""
+def case1_3d_steps(nx: int, ny: int, nz: int, s1: float, s2: float, phi1: float, phi2: float):
+    """The steps of the 3D range computation for every i, as the paper's hand computations
+    of Test suite 3 list them: [(i, C_x, (j_lo, j_hi), {j: (C_y, (k_lo, k_hi),
+    {k: length})})], (j_lo, j_hi) and (k_lo, k_hi) the open intervals of eqs.
+    restriction_j_3D and restriction_k_3D_1 (the two k intervals intersected)."""
     assert 0.0 < phi1 < math.pi / 2 and 0.0 < phi2 < math.pi / 2
     c1_, s1_ = math.cos(phi1), math.sin(phi1)
     c2_, s2_ = math.cos(phi2), math.sin(phi2)
     wx, wy, wz = 1.0 / (c2_ * c1_), 1.0 / (c2_ * s1_), 1.0 / s2_   # a unit's extent in t
-    out = {}
+    steps = []
     for i in range(nx):
         cx = (i - nx / 2 + s1 * s1_ + s2 * s2_ * c1_) * wx
         c1 = ny / 2 - s1 * c1_ + s2 * s2_ * s1_ - cx * c2_ * s1_
         c2 = nz / 2 - s2 * c2_ - cx * s2_
-        for j in _open_integers(c1 - math.tan(phi1) - 1.0, c1, ny):
+        jr = (c1 - math.tan(phi1) - 1.0, c1)
+        js = {}
+        for j in _open_integers(*jr, ny):
             cy = (ny / 2 - j - s1 * c1_ + s2 * s2_ * s1_) * wy
             c3 = nz / 2 - s2 * c2_ - cy * s2_
-            ka = set(_open_integers(c2 - math.tan(phi2) / c1_ - 1.0, c2, nz))
-            kb = set(_open_integers(c3 - 1.0, c3 + math.tan(phi2) / s1_, nz))
-            for k in sorted(ka & kb):
+            kr = (max(c2 - math.tan(phi2) / c1_ - 1.0, c3 - 1.0), min(c2, c3 + math.tan(phi2) / s1_))
+            ks = {}
+            for k in _open_integers(*kr, nz):
                 cz = (nz / 2 - k - s2 * c2_) * wz
                 c_low = max(cx, cy - wy, cz - wz)
                 c_up = min(cx + wx, cy, cz)
-                out[(k, j, i)] = c_up - c_low
-    return out
+                ks[k] = c_up - c_low
+            js[j] = (cy, kr, ks)
+        steps.append((i, cx, jr, js))
+    return steps
+
+
+def case1_3d(nx: int, ny: int, nz: int, s1: float, s2: float, phi1: float, phi2: float):
+    """Units (k, j, i) -> length of the 3D ray (s1, s2, phi1, phi2), both angles in
+    (0, pi/2), listed by i (eqs. restriction_j_3D, restriction_k_3D_1) with
+    C_up - C_low (eq. range_length_3D)."""
+    return {(k, j, i): ln for i, _, _, js in case1_3d_steps(nx, ny, nz, s1, s2, phi1, phi2)
+            for j, (_, _, ks) in js.items() for k, ln in ks.items()}
 
 
 def to_1d(units: dict, nx: int, ny: int):

@@ -145,3 +145,54 @@ def test_host_walk_slabs_equal_the_paper_ranges(walker, tmp_path, d3):  # noqa: 
             rs = {I: v for I, v in ref.items() if I % nx == i}
             _assert_same(gs, rs, 1e-10, f"ray {r} slab i={i}")
         assert len(got) == len(ref)
+
+
+# ------------------------------------------------------------------ the paper's hand computations
+
+R2, R3 = math.sqrt(2.0), math.sqrt(3.0)
+
+
+def test_ranges_reproduce_hand_computation_of_test_suite_1():
+    """Test suite 1 (2D parallel beam, 3 x 3 image, ray (1, pi/4)) computed by hand slab
+    by slab: C_x, C_1, the valid j, C_y and the lengths.  For i = 1 the paper prints
+    C_1 = 5/2 - 3 sqrt(2)/2; its own definition gives 2 - sqrt(2) (the range, j = 0, is
+    the same either way)."""
+    steps = ranges.case1_2d_steps(3, 3, 1.0, PI / 4)
+    want = [
+        (0, -3 * R2 / 2 + 1, 3 - R2, {0: (3 * R2 / 2 - 1, 2 - R2), 1: (R2 / 2 - 1, 2 * R2 - 2)}),
+        (1, -R2 / 2 + 1, 2 - R2, {0: (3 * R2 / 2 - 1, 2 * R2 - 2)}),
+        (2, None, None, {}),
+    ]
+    for (i, cx, c1, js), (wi, wcx, wc1, wjs) in zip(steps, want):
+        assert i == wi and sorted(js) == sorted(wjs), (i, js)
+        if wcx is not None:
+            assert abs(cx - wcx) < 1e-12 and abs(c1 - wc1) < 1e-12
+        for j, (cy, ln) in wjs.items():
+            assert abs(js[j][0] - cy) < 1e-12 and abs(js[j][1] - ln) < 1e-12
+
+
+def test_ranges_reproduce_hand_computation_of_test_suite_3():
+    """Test suite 3 (3D parallel beam, 3 x 3 x 3 image, ray (0, 0, pi/4, pi/4)) by hand:
+    C_x, the interval of j, C_y, the interval of k and the lengths, slab by slab.  The ray
+    runs through grid edges, where FP64 puts interval ends within 1e-15 of the integers
+    the exact values hit and admits units with slivers of ~1e-16; the exact hand
+    computation's sets are those of length > 1e-12 (zero-length contacts are no hits)."""
+    steps = ranges.case1_3d_steps(3, 3, 3, 0.0, 0.0, PI / 4, PI / 4)
+    steps = [(i, cx, jr, {j: (cy, kr, {k: ln for k, ln in ks.items() if ln > 1e-12})
+                          for j, (cy, kr, ks) in js.items() if any(ln > 1e-12 for ln in ks.values())})
+             for i, cx, jr, js in steps]
+    want = [
+        (0, -3.0, (1.0, 3.0), {2: (-1.0, ((1 + R2) / 2, (3 + 3 * R2) / 2), {2: 3 * R2 / 2 - 1})}),
+        (1, -1.0, (0.0, 2.0), {1: (1.0, ((1 - R2) / 2, (3 + R2) / 2), {0: 1 - R2 / 2, 1: R2, 2: 1 - R2 / 2})}),
+        (2, 1.0, (-1.0, 1.0), {0: (3.0, ((1 - 3 * R2) / 2, (3 - R2) / 2), {0: 3 * R2 / 2 - 1})}),
+    ]
+    for (i, cx, jr, js), (wi, wcx, wjr, wjs) in zip(steps, want):
+        assert i == wi and abs(cx - wcx) < 1e-12
+        assert abs(jr[0] - wjr[0]) < 1e-12 and abs(jr[1] - wjr[1]) < 1e-12
+        assert sorted(js) == sorted(wjs), (i, js)
+        for j, (cy, kr, ks) in wjs.items():
+            gcy, gkr, gks = js[j]
+            assert abs(gcy - cy) < 1e-12 and abs(gkr[0] - kr[0]) < 1e-12 and abs(gkr[1] - kr[1]) < 1e-12
+            assert sorted(gks) == sorted(ks), (i, j, gks)
+            for k, ln in ks.items():
+                assert abs(gks[k] - ln) < 1e-12
