@@ -392,12 +392,29 @@ struct AttAdjVisit {
     double scale, g, A;
     __device__ __forceinline__ void one(int32_t I, double l)
     {
-        if (!(l > 0.0)) return;
-        const float m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, I * 4, 0, 0));
-        const double lp = l * scale, x = (double)m * lp;
-        const float w = att_weight(m, (float)lp, (float)x);
-        unsafeAtomicAdd(img + I, (float)(g * (double)(__expf(-(float)A) * w)));
-        A += x;
+        const bool hit = l > 0.0;
+        float val = 0.0f;
+        if (hit) {
+            const float m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, I * 4, 0, 0));
+            const double lp = l * scale, x = (double)m * lp;
+            const float w = att_weight(m, (float)lp, (float)x);
+            val = (float)(g * (double)(__expf(-(float)A) * w));
+            A += x;
+        }
+        // neighbouring lanes (neighbouring detector columns) often add to the same unit:
+        // each run of lanes with one unit adds its sum with one atomic, from its first lane
+        const uint32_t lane = __lane_id();
+        const uint64_t act = __builtin_amdgcn_ballot_w64(true);
+        const int32_t key = hit ? I : -1;
+        const int32_t kn = __shfl_down(key, 1);
+        const bool nxt = lane < 63 && ((act >> (lane + 1)) & 1ull);
+        const uint64_t cont = __builtin_amdgcn_ballot_w64(hit && nxt && kn == key);
+        float acc = val, v = val;
+        for (uint64_t run = cont, d = 1; run != 0; run &= cont >> d, ++d) {
+            v = __shfl_down(v, 1);
+            if ((run >> lane) & 1ull) acc += v;
+        }
+        if (hit && !(lane > 0 && ((cont >> (lane - 1)) & 1ull))) unsafeAtomicAdd(img + I, acc);
     }
     __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
     {

@@ -62,6 +62,38 @@ def test_attenuated_parity(X, name):
     H.assert_within_bar(adj, aref, ascl, what=f"attenuated adjoint {name}")
 
 
+MANY_ROW_SCANS = [
+    ("cone_flat", dict(nx=35, ny=17, nz=40, dx=1.0, dy=1.1, dz=0.9, cx=0.5, cy=-1.0, cz=0.3),
+     dict(kind="cone_flat", angles=np.linspace(0.2, 2 * np.pi, 5, endpoint=False), ncols=23, nrows=70, du=1.3,
+          dv=0.8, sod=90.0, sdd=140.0)),
+    ("cone_arc", dict(nx=21, ny=33, nz=36, dx=1.0, dy=1.0, dz=1.0, cx=0.0, cy=0.0, cz=0.0),
+     dict(kind="cone_arc", angles=np.linspace(0.0, 2 * np.pi, 4, endpoint=False), ncols=19, nrows=131,
+          du=0.01, dv=0.004, sod=85.0, sdd=130.0, view_z=np.linspace(-3, 3, 4))),
+]
+
+
+@pytest.mark.parametrize("name,grid,scan", MANY_ROW_SCANS, ids=[c[0] for c in MANY_ROW_SCANS])
+def test_attenuated_adjoint_many_rows(X, name, grid, scan):
+    """Cone plans of 70 and 131 rows on grids of several 32-unit transpose tiles with a
+    ragged tail: the adjoint's y-fastest partial volume, its transposes and the merged
+    atomics of neighbouring lanes, against the oracle's adjoint for two images with their
+    own maps and with one shared map, and a view of zeros."""
+    plan = X.Plan(grid, scan)
+    rng = np.random.default_rng(41)
+    shape = tuple(plan.image_shape)
+    mu = rng.uniform(0, 0.3, size=(2,) + shape).astype(np.float32)
+    w = rng.normal(size=(2,) + tuple(plan.sino_shape)).astype(np.float32)
+    w[1, 1] = 0.0   # a view of zero values (rays that return before walking)
+    p, th = ogeom.expand(scan)
+    per = plan.adjoint_attenuated(torch.from_numpy(w).to(DEV), torch.from_numpy(mu).to(DEV)).cpu().numpy()
+    shared = plan.adjoint_attenuated(torch.from_numpy(w).to(DEV), torch.from_numpy(mu[0]).to(DEV)).cpu().numpy()
+    for b in range(2):
+        for got, m, what in ((per[b], mu[b], "own map"), (shared[b], mu[0], "shared map")):
+            ref = ocore.adjoint_att_lines(grid, p, th, w[b].astype(np.float64), m.astype(np.float64))
+            scl = ocore.adjoint_att_lines(grid, p, th, np.abs(w[b]).astype(np.float64), m.astype(np.float64))
+            H.assert_within_bar(got, ref, scl, what=f"many-row adjoint {name} image {b} {what}")
+
+
 def test_attenuated_forward_wide_grid(X):
     """A grid wider than 256 units: the attenuated forward takes the walk's flat form."""
     from tests.test_gpu_parity import WIDE_SCANS
