@@ -23,6 +23,15 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// two floats rounded to BF16 (nearest even) and packed, low half first: one instruction
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
 
 constexpr int kCB = 256;
 
@@ -406,29 +415,24 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
             float xv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) xv[e] = xp[tap_off[e]];
-            bf16x8 bx;
+            // no masks: the weights of contraction indices past tap 8 are zero, and a
+            // pixel past the region (which read pixel 0) is not stored
+            u32x4 bxw;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) bx[e] = (__bf16)(valid && kb * 8 + e < 9 ? xv[e] : 0.0f);
-            const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bx, f32x16{}, 0, 0, 0);
+            for (int e = 0; e < 4; ++e) bxw[e] = pk_bf16(xv[2 * e], xv[2 * e + 1]);
+            const f32x16 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, __builtin_bit_cast(bf16x8, bxw), f32x16{}, 0, 0, 0);
             if (valid) {
                 // channels 8 g + 4 kb .. + 3 of pixel P (h1 is zero outside the image;
                 // a tile whose x ring lies inside the image needs no mask)
-                if (interior) {
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) dst[q] = (__bf16)d[4 * g + q];
-                    }
-                } else {
+                bool in = true;
+                if (!interior) {
                     const int32_t iy = Y0 - 2 + pr, ix = X0 - 2 + pc;
-                    const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+                    in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
+                }
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        __bf16* dst = &sh1[P * kH1S + 8 * g + 4 * kb];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) dst[q] = (__bf16)(in ? d[4 * g + q] : 0.0f);
-                    }
+                for (int g = 0; g < 4; ++g) {
+                    const uint32_t w0 = pk_bf16(d[4 * g], d[4 * g + 1]), w1 = pk_bf16(d[4 * g + 2], d[4 * g + 3]);
+                    *reinterpret_cast<uint2*>(&sh1[P * kH1S + 8 * g + 4 * kb]) = make_uint2(in ? w0 : 0u, in ? w1 : 0u);
                 }
             }
         }
@@ -452,24 +456,21 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int32_t R = wv + 4 * j;
-            bf16x8 b0, b1;
-            if (interior) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    b0[e] = (__bf16)h2[j][e];
-                    b1[e] = (__bf16)h2[j][8 + e];
-                }
-            } else {
+            bool in = true;
+            if (!interior) {
                 const int32_t iy = Y0 - 1 + R, ix = X0 - 1 + m;
-                const bool in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    b0[e] = (__bf16)(in ? h2[j][e] : 0.0f);
-                    b1[e] = (__bf16)(in ? h2[j][8 + e] : 0.0f);
-                }
+                in = iy >= 0 && iy < H && ix >= 0 && ix < Wd;
             }
-            f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], b0, f32x16{}, 0, 0, 0);
-            u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], b1, u, 0, 0, 0);
+            u32x4 w0, w1;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t p0 = pk_bf16(h2[j][2 * e], h2[j][2 * e + 1]);
+                const uint32_t p1 = pk_bf16(h2[j][8 + 2 * e], h2[j][8 + 2 * e + 1]);
+                w0[e] = in ? p0 : 0u;
+                w1[e] = in ? p1 : 0u;
+            }
+            f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[0], __builtin_bit_cast(bf16x8, w0), f32x16{}, 0, 0, 0);
+            u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[1], __builtin_bit_cast(bf16x8, w1), u, 0, 0, 0);
             // D[i] of lane l: tap 8 (i / 4) + 4 kb + i % 4 (taps 0..8 are used), pixel m
 #pragma unroll
             for (int i = 0; i < 4; ++i) su[((4 * kb + i) * kH2R + R) * kH2C + m] = u[i];
