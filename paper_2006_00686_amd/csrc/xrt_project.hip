@@ -676,20 +676,56 @@ __global__ __launch_bounds__(kBlock) void k_forward_il(DevPlan P, const float* _
 }
 
 // The attenuated forward of one image from its (f, mu) pairs (NEST: the walk's form).
-template <int DIM, int MODE, bool NEST>
+// ZP: column packets (packet_cols = 1, 64 rows of one detector column per wavefront,
+// flat walk) over pairs held z fastest ([y][x][z]), as the plain forward's column packets.
+template <int DIM, int MODE, bool NEST, bool ZP = false>
 __global__ __launch_bounds__(kBlock) void k_forward_att_pairs(DevPlan P, const float* __restrict__ pairs,
                                                                float* __restrict__ sino)
 {
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= P.n_rays) return;
+    int32_t r;
+    if constexpr (ZP) {
+        r = packet_ray(P, (uint64_t)blockIdx.x * kBlock + threadIdx.x);
+        if (r < 0) return;
+    } else {
+        r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+        if (r >= P.n_rays) return;
+    }
     Ray R;
     make_ray<DIM, MODE>(P, r, R);
 #pragma unroll
     for (int a = 0; a < 3; ++a) R.w[a] = -R.w[a];   // from the detector side back
+    if constexpr (ZP) {
+        R.st[0] = P.nz;
+        R.st[1] = P.nx * P.nz;
+        R.st[2] = 1;
+    }
     AttFwdPairVisit v{image_rsrc(pairs, (int32_t)(P.n_units * 8)), R.scale, 0.0, 0.0};
     walk<DIM, NEST>(P, R, v);
     v.consume();
     sino[r] = (float)v.acc;
+}
+
+// pairs[y][x][z] = (img[z][y][x], mu[z][y][x]) (one y per block row of tiles: 32 z x 32 x)
+__global__ __launch_bounds__(kBlock) void k_att_pairs_zfast(const float* __restrict__ img, const float* __restrict__ mu,
+                                                             float2* __restrict__ out, int32_t nx, int32_t ny,
+                                                             int32_t nz, int32_t ztiles)
+{
+    __shared__ float2 tile[32][33];
+    const int32_t y = blockIdx.y / ztiles;
+    const int32_t z0 = (blockIdx.y - y * ztiles) * 32, x0 = blockIdx.x * 32;
+    const int32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int32_t zz = ty; zz < 32; zz += kBlock / 32) {
+        const int32_t z = z0 + zz, x = x0 + tx;
+        if (z < nz && x < nx) {
+            const int64_t at = ((int64_t)z * ny + y) * nx + x;
+            tile[zz][tx] = make_float2(img[at], mu[at]);
+        }
+    }
+    __syncthreads();
+    for (int32_t xx = ty; xx < 32; xx += kBlock / 32) {
+        const int32_t x = x0 + xx, z = z0 + tx;
+        if (z < nz && x < nx) out[((int64_t)y * nx + x) * nz + z] = tile[tx][xx];
+    }
 }
 
 // pairs[i] = (img[i], mu[i])
@@ -1095,7 +1131,26 @@ xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const f
 {
     const DevPlan& P = p->dp;
     const unsigned pblocks = (unsigned)std::min<int64_t>((P.n_units + kBlock - 1) / kBlock, 65536);
+    // column packets as in the plain forward (cone plans with 64 rows or more)
+    const bool zp = P.dim == 3 && P.packet_cols == 1 && (P.mode == MODE_DIVERGENT || P.mode == MODE_ARC);
     for (int b = 0; b < batch; ++b) {
+        if (zp) {
+            const int32_t ztiles = (P.nz + 31) / 32;
+            hipLaunchKernelGGL(k_att_pairs_zfast, dim3((unsigned)((P.nx + 31) / 32), (unsigned)(ztiles * P.ny)),
+                               dim3(kBlock), 0, s, img + (int64_t)b * P.n_units, mu + (int64_t)b * mu_stride,
+                               (float2*)p->d_att, P.nx, P.ny, P.nz, ztiles);
+            xrt_status st = hip_fail(hipGetLastError(), "attenuation pairs launch");
+            if (st != XRT_OK) return st;
+            const dim3 g((unsigned)((forward_threads(P) + kBlock - 1) / kBlock));
+            if (P.mode == MODE_DIVERGENT)
+                hipLaunchKernelGGL((k_forward_att_pairs<3, MODE_DIVERGENT, false, true>), g, dim3(kBlock), 0, s, P,
+                                   (const float*)p->d_att, sino + (int64_t)b * P.n_rays);
+            else
+                hipLaunchKernelGGL((k_forward_att_pairs<3, MODE_ARC, false, true>), g, dim3(kBlock), 0, s, P,
+                                   (const float*)p->d_att, sino + (int64_t)b * P.n_rays);
+            if ((st = hip_fail(hipGetLastError(), "kernel launch")) != XRT_OK) return st;
+            continue;
+        }
         hipLaunchKernelGGL(k_att_pairs, dim3(pblocks), dim3(kBlock), 0, s, img + (int64_t)b * P.n_units,
                            mu + (int64_t)b * mu_stride, (float2*)p->d_att, P.n_units);
         xrt_status st = hip_fail(hipGetLastError(), "attenuation pairs launch");

@@ -73,15 +73,25 @@ MANY_ROW_SCANS = [
 
 
 @pytest.mark.parametrize("name,grid,scan", MANY_ROW_SCANS, ids=[c[0] for c in MANY_ROW_SCANS])
-def test_attenuated_adjoint_many_rows(X, name, grid, scan):
-    """Cone plans of 70 and 131 rows on grids of several 32-unit transpose tiles with a
-    ragged tail: the adjoint's y-fastest partial volume, its transposes and the merged
-    atomics of neighbouring lanes, against the oracle's adjoint for two images with their
-    own maps and with one shared map, and a view of zeros."""
+def test_attenuated_many_rows(X, name, grid, scan):
+    """Cone plans of 70 and 131 rows (column packets: a partial packet per column) on grids
+    of several 32-unit tiles with a ragged tail.  The forward reads z-fastest (f, mu) pairs;
+    the adjoint adds into the y-fastest partial volume with the merged atomics of
+    neighbouring lanes.  Against the oracle for two images with their own maps and with one
+    shared map, and (adjoint) a view of zeros."""
     plan = X.Plan(grid, scan)
+    assert plan.tuning()["packet_cols"] == 1
     rng = np.random.default_rng(41)
     shape = tuple(plan.image_shape)
     mu = rng.uniform(0, 0.3, size=(2,) + shape).astype(np.float32)
+    img = rng.uniform(0, 1, size=(2,) + shape).astype(np.float32)
+    fwd = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu).to(DEV)).cpu().numpy()
+    fsh = plan.forward_attenuated(torch.from_numpy(img).to(DEV), torch.from_numpy(mu[0]).to(DEV)).cpu().numpy()
+    for b in range(2):
+        ref, scl = _bar(grid, scan, img[b], mu[b])
+        H.assert_within_bar(fwd[b], ref, scl, what=f"many-row forward {name} image {b}")
+    ref, scl = _bar(grid, scan, img[1], mu[0])
+    H.assert_within_bar(fsh[1], ref, scl, what=f"many-row forward {name} shared map")
     w = rng.normal(size=(2,) + tuple(plan.sino_shape)).astype(np.float32)
     w[1, 1] = 0.0   # a view of zero values (rays that return before walking)
     p, th = ogeom.expand(scan)
