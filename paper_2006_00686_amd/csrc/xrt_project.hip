@@ -1141,7 +1141,9 @@ xrt_status launch_forward_att_pairs(const xrt_plan* p, const float* img, const f
                                (float2*)p->d_att, P.nx, P.ny, P.nz, ztiles);
             xrt_status st = hip_fail(hipGetLastError(), "attenuation pairs launch");
             if (st != XRT_OK) return st;
-            const dim3 g((unsigned)((forward_threads(P) + kBlock - 1) / kBlock));
+            const uint64_t nb64 = (forward_threads(P) + kBlock - 1) / kBlock;
+            if (nb64 > 0x7FFFFFF0ull) { set_error("attenuated forward launch too large"); return XRT_E_SIZE; }
+            const dim3 g((unsigned)nb64);
             if (P.mode == MODE_DIVERGENT)
                 hipLaunchKernelGGL((k_forward_att_pairs<3, MODE_DIVERGENT, false, true>), g, dim3(kBlock), 0, s, P,
                                    (const float*)p->d_att, sino + (int64_t)b * P.n_rays);
