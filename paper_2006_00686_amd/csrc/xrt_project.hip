@@ -204,6 +204,30 @@ __device__ __forceinline__ void atomic_add_runs(float* img, int32_t I, bool hit,
     if (hit && !(lane > 0 && ((cont >> (lane - 1)) & 1ull))) unsafeAtomicAdd(img + I, acc);
 }
 
+// Before the runs merge: a lane's second unit of a slab is often the first unit of a
+// neighbouring lane (the neighbouring ray is already past the boundary this one crosses).
+// Such a value is handed to that lane, whose first-unit run then adds it, and the lane
+// keeps no atomic for it (keep2 = false).  A value goes to the lane above (lane + 1) if
+// that lane takes it, else to the lane below if that one does -- never to both.
+__device__ __forceinline__ void hand_over(int32_t I1, bool hit1, float& v1, int32_t I2, bool hit2, float v2,
+                                          bool& keep2)
+{
+    const uint32_t lane = __lane_id();
+    const uint64_t act = __builtin_amdgcn_ballot_w64(true);
+    const int32_t k2 = hit2 ? I2 : -2;
+    const int32_t kb = __shfl_up(k2, 1), ka = __shfl_down(k2, 1);
+    const float vb = __shfl_up(v2, 1), va = __shfl_down(v2, 1);
+    const bool has_b = lane > 0 && ((act >> (lane - 1)) & 1ull);
+    const bool has_a = lane < 63 && ((act >> (lane + 1)) & 1ull);
+    const bool tb = hit1 && has_b && kb == I1;                      // from the lane below
+    const uint64_t TB = __builtin_amdgcn_ballot_w64(tb);
+    const bool ta = hit1 && has_a && ka == I1 && !(lane + 2 < 64 && ((TB >> (lane + 2)) & 1ull));
+    const uint64_t TA = __builtin_amdgcn_ballot_w64(ta);
+    if (tb) v1 += vb;
+    if (ta) v1 += va;
+    keep2 = hit2 && !((lane < 63 && ((TB >> (lane + 1)) & 1ull)) || (lane > 0 && ((TA >> (lane - 1)) & 1ull)));
+}
+
 struct ScatterVisit {
     static constexpr int32_t kIndexScale = 1;
     float* img;
@@ -214,14 +238,20 @@ struct ScatterVisit {
     }
     __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
     {
-        one(I1, l1);
-        one(I2, l2);
+        float v1 = (float)(gw * l1);
+        bool keep2;
+        hand_over(I1, l1 > 0.0, v1, I2, l2 > 0.0, (float)(gw * l2), keep2);
+        atomic_add_runs(img, I1, l1 > 0.0, v1);
+        atomic_add_runs(img, I2, keep2, (float)(gw * l2));
     }
     __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
                                           double l3)
     {
-        one(I1, l1);
-        one(I2, l2);
+        float v1 = (float)(gw * l1);
+        bool keep2;
+        hand_over(I1, l1 > 0.0, v1, I2, l2 > 0.0, (float)(gw * l2), keep2);
+        atomic_add_runs(img, I1, l1 > 0.0, v1);
+        atomic_add_runs(img, I2, keep2, (float)(gw * l2));
         one(I3, l3);
     }
 };
@@ -413,29 +443,42 @@ struct AttAdjVisit {
     float* img;
     __amdgpu_buffer_rsrc_t rm;
     double scale, g, A;
-    __device__ __forceinline__ void one(int32_t I, double l)
+    // the piece's value g exp(-A) w, A then taking the piece (0 for a candidate not hit)
+    __device__ __forceinline__ float value(int32_t I, double l)
     {
-        const bool hit = l > 0.0;
         float val = 0.0f;
-        if (hit) {
+        if (l > 0.0) {
             const float m = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rm, I * 4, 0, 0));
             const double lp = l * scale, x = (double)m * lp;
             const float w = att_weight(m, (float)lp, (float)x);
             val = (float)(g * (double)(__expf(-(float)A) * w));
             A += x;
         }
-        atomic_add_runs(img, I, hit, val);
+        return val;
+    }
+    __device__ __forceinline__ void one(int32_t I, double l)
+    {
+        const float val = value(I, l);
+        atomic_add_runs(img, I, l > 0.0, val);
     }
     __device__ __forceinline__ void two(int32_t I1, double l1, int32_t I2, double l2)
     {
-        one(I1, l1);
-        one(I2, l2);
+        float v1 = value(I1, l1);
+        const float v2 = value(I2, l2);
+        bool keep2;
+        hand_over(I1, l1 > 0.0, v1, I2, l2 > 0.0, v2, keep2);
+        atomic_add_runs(img, I1, l1 > 0.0, v1);
+        atomic_add_runs(img, I2, keep2, v2);
     }
     __device__ __forceinline__ void three(int32_t I1, double l1, int32_t I2, double l2, int32_t I3,
                                           double l3)
     {
-        one(I1, l1);
-        one(I2, l2);
+        float v1 = value(I1, l1);
+        const float v2 = value(I2, l2);
+        bool keep2;
+        hand_over(I1, l1 > 0.0, v1, I2, l2 > 0.0, v2, keep2);
+        atomic_add_runs(img, I1, l1 > 0.0, v1);
+        atomic_add_runs(img, I2, keep2, v2);
         one(I3, l3);
     }
 };
