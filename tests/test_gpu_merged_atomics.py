@@ -4,7 +4,8 @@ sums its values and adds them from its first lane.  The workloads' detectors giv
 one or two lanes; these scans sample the detector ten times finer than the grid (runs of
 about ten lanes, so every pass of the run sum is taken), with every seventh sinogram value
 zero (lanes that leave before the walk and split runs) and rays that leave the grid in
-different slabs.  Against the FP64 oracle's adjoints, element by element."""
+different slabs.  Against the FP64 oracle's adjoints, element by element; and the plain
+scatter of the 256^3 cone workload at full size on three views."""
 import numpy as np
 import pytest
 
@@ -73,3 +74,24 @@ def test_attenuated_adjoint_with_long_runs(X):
     scl = ocore.adjoint_att_lines(G3, p, th, np.abs(w).astype(np.float64), mu.astype(np.float64))
     assert np.count_nonzero(scl) > 0.9 * scl.size
     H.assert_within_bar(got, ref, scl, what="attenuated adjoint")
+
+
+def test_cone_256_scatter_three_views(X):
+    """The plain scatter adjoint of the 256^3 cone workload at full size on a sinogram that
+    is zero outside three views, against the oracle's adjoint of those views' rays, voxel
+    by voxel."""
+    cfg = inputs.workload("cone_256")
+    plan = X.Plan(cfg["grid"], cfg["scan"])
+    rng = np.random.default_rng(17)
+    views = np.sort(rng.choice(len(cfg["scan"]["angles"]), 3, replace=False))
+    w = np.zeros(tuple(plan.sino_shape), dtype=np.float32)
+    w[views] = rng.normal(size=(3,) + tuple(plan.sino_shape)[1:]).astype(np.float32)
+    got = plan.adjoint(torch.from_numpy(w).to(DEV), mode="scatter").cpu().numpy()
+    sub = dict(cfg["scan"])
+    sub["angles"] = np.asarray(cfg["scan"]["angles"])[views]
+    p, th = ogeom.expand(sub)
+    wv = w[views].reshape(-1).astype(np.float64)
+    ref = ocore.adjoint_lines(cfg["grid"], p, th, wv)
+    scl = ocore.adjoint_lines(cfg["grid"], p, th, np.abs(wv))
+    assert np.count_nonzero(scl) > 0.5 * scl.size
+    H.assert_within_bar(got, ref, scl, what="cone_256 scatter, three views")
